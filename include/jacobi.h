@@ -1,0 +1,159 @@
+/*
+ * jacobi.h -- C-ABI of libjacobi: temporally blocked 3D 7-point Jacobi on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Wittmann, Hager, Treibig, Wellein, "Leveraging shared caches for
+ * parallel temporal blocking of stencil codes on multicore processors and
+ * clusters", 2010):
+ *   - Sect. 1.1, Eq. (1): one sweep updates every interior cell of an
+ *     (nx+2) x (ny+2) x (nz+2) box as
+ *         B[i,j,k] = (A[i-1,j,k] + A[i+1,j,k] + A[i,j-1,k] + A[i,j+1,k]
+ *                     + A[i,j,k-1] + A[i,j,k+1]) / 6,
+ *     successive sweeps writing grids A and B in turn; the outer layer of the
+ *     box is a fixed Dirichlet boundary (the boundary value problem).
+ *   - Sect. 2.1: temporal blocking -- t sweeps are applied per trip through
+ *     memory; the optional "compressed grid" keeps a single grid and stores
+ *     each trip's result shifted by (-t,-t,-t) and (+t,+t,+t) alternately.
+ *   - Sect. 2.2, Eq. (3): relaxed synchronization through per-worker progress
+ *     counters instead of global barriers.
+ *
+ * Arithmetic: the six neighbours are summed as a left fold in the order above
+ * (i-1, i+1, j-1, j+1, k-1, k+1), then multiplied by the rounded constant
+ * fl(1/6); IEEE round-to-nearest, no fused multiply-add.  FP64 results are
+ * bitwise identical for every t, layout and tile shape.
+ *
+ * Memory: every device buffer is owned by the caller (e.g. allocated with
+ * PyTorch); the library allocates no device memory and owns only the host
+ * handle.  Box layout: element (i,j,k) of a frame with origin O and strides
+ * (1, px, py) is O[k*py + j*px + i]; i is contiguous.
+ *
+ * Errors: every function returns 0 (JACOBI_OK) or a negative jacobi_status and
+ * never aborts; jacobi_last_error() gives a message for the calling thread.
+ * Kernel launches are asynchronous on the descriptor's stream; faults of a
+ * launched kernel and watchdog time-outs surface at the next call that
+ * synchronizes (jacobi_residual, jacobi_solve, jacobi_sync).
+ *
+ * A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef JACOBI_H
+#define JACOBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    JACOBI_OK = 0,
+    JACOBI_EINVAL = -1,       /* bad argument (null, size, range, alignment) */
+    JACOBI_EUNSUPPORTED = -2, /* valid request this build does not provide */
+    JACOBI_EWORKSPACE = -3,   /* workspace missing or too small */
+    JACOBI_EHIP = -4,         /* HIP runtime error (launch or kernel fault) */
+    JACOBI_ETIMEOUT = -5,     /* a progress-flag wait exceeded its spin bound */
+    JACOBI_ESTATE = -6        /* call not valid in the handle's state */
+} jacobi_status;
+
+typedef enum {
+    JACOBI_F64 = 0,        /* FP64 sweeps */
+    JACOBI_F32_REFINED = 1 /* FP32 sweeps of the correction equation, FP64
+                              residual and FP64 defect-correction update */
+} jacobi_dtype;
+
+typedef enum {
+    JACOBI_LAYOUT_AB = 0,        /* two grids, written in turn (Sect. 1.1) */
+    JACOBI_LAYOUT_COMPRESSED = 1 /* one grid, shifted stores (Sect. 2.1) */
+} jacobi_layout;
+
+typedef struct {
+    int64_t nx, ny, nz;  /* interior dims, each >= 1; box is (n+2) per axis */
+    int32_t dtype;       /* jacobi_dtype */
+    int32_t layout;      /* jacobi_layout */
+    int32_t t;           /* sweeps per trip, 1..8 (0 = library default 4) */
+    int32_t tile_rows;   /* j-rows per tile: 0 = default for t, else one of
+                            the compiled shapes (jacobi_tile_supported) */
+    int32_t rows_per_wave; /* 0 = default; with tile_rows selects the shape */
+    int32_t seg_len;     /* k planes per tile segment, 0 = automatic */
+    int32_t inner_sweeps;/* JACOBI_F32_REFINED: FP32 sweeps per outer
+                            correction step (0 = 32) */
+    int32_t reserved;
+    void *grid0;         /* FP64 grid buffer (device); see jacobi_grid_bytes */
+    void *grid1;         /* second FP64 grid for JACOBI_LAYOUT_AB, else NULL */
+    void *workspace;     /* device scratch owned by the caller */
+    size_t workspace_bytes;
+    void *stream;        /* hipStream_t (NULL = default stream) */
+} jacobi_desc;
+
+typedef struct jacobi_s jacobi_t;
+
+/* Bytes each grid buffer must hold for `d` (dims, layout and t are read).
+ * AB: (nx+2)(ny+2)(nz+2) doubles.  COMPRESSED: the box plus t shift planes per
+ * axis, (nx+2+t)(ny+2+t)(nz+2+t) doubles.  Errors: JACOBI_EINVAL. */
+int jacobi_grid_bytes(const jacobi_desc *d, size_t *bytes);
+
+/* Bytes of device workspace `d` needs (flags, reduction partials, and for
+ * JACOBI_F32_REFINED two FP32 correction grids and an FP32 right-hand side).
+ * The workspace must be 256-byte aligned.  Errors: JACOBI_EINVAL. */
+int jacobi_workspace_size(const jacobi_desc *d, size_t *bytes);
+
+/* Validates `d` and creates a handle.  The caller must have written the
+ * initial box (boundary values and initial interior) into the frame that
+ * jacobi_current() reports for the new handle (for AB: grid0 with strides
+ * (1, nx+2, (nx+2)(ny+2)); for COMPRESSED: grid0 at the offset reported).
+ * May launch set-up kernels on the stream (AB: copies the box into grid1 so
+ * both grids carry the boundary).  Errors: JACOBI_EINVAL (null pointers,
+ * dims < 1 or > 2^20, misaligned buffers), JACOBI_EUNSUPPORTED (t or tile
+ * shape not compiled), JACOBI_EWORKSPACE, JACOBI_EHIP. */
+int jacobi_create(const jacobi_desc *d, jacobi_t **out);
+
+/* Applies n_steps Jacobi sweeps (JACOBI_F32_REFINED: n_steps FP32 inner
+ * sweeps, grouped into outer correction steps of inner_sweeps) to the
+ * current iterate.  Asynchronous on the stream.  n_steps >= 0. */
+int jacobi_sweep(jacobi_t *h, int64_t n_steps);
+
+/* ||fold(u nbrs) - 6u||_2 over the interior of the current iterate, FP64,
+ * deterministic fixed-order reduction.  Synchronizes the stream; reports a
+ * pending kernel fault (JACOBI_EHIP) or watchdog time-out (JACOBI_ETIMEOUT).
+ * Optional `maxabs` receives max |r|. */
+int jacobi_residual(jacobi_t *h, double *l2, double *maxabs);
+
+/* Runs sweeps until ||r||_2 <= rel_tol * r0, checking every `check_every`
+ * sweeps, at most max_sweeps.  r0 <= 0 means: the residual of the current
+ * iterate.  Outputs the sweeps done and the final residual norm. */
+int jacobi_solve(jacobi_t *h, double rel_tol, double r0, int64_t max_sweeps,
+                 int64_t check_every, int64_t *sweeps_done, double *final_l2);
+
+/* Waits for the stream and reports pending errors as jacobi_residual does. */
+int jacobi_sync(jacobi_t *h);
+
+/* Pointer to logical cell (0,0,0) of the current iterate and its strides in
+ * elements {1, px, py}.  Valid until the next jacobi_sweep. */
+int jacobi_current(jacobi_t *h, void **origin, int64_t strides[3]);
+
+/* Sweeps applied so far and the trip configuration in use. */
+int jacobi_info(jacobi_t *h, int64_t *sweeps_done, int32_t *t,
+                int32_t *tile_rows, int32_t *seg_len);
+
+/* Releases the handle; never frees caller buffers. */
+int jacobi_destroy(jacobi_t *h);
+
+/* Message of the last error of the calling thread ("" if none). */
+const char *jacobi_last_error(void);
+
+/* 1 if the trip kernel is compiled for sweeps-per-trip t with tiles of
+ * `tile_rows` j-rows made of `rows_per_wave`-row waves, else 0. */
+int jacobi_tile_supported(int32_t dtype, int32_t t, int32_t tile_rows,
+                          int32_t rows_per_wave);
+
+/* ---- bandwidth probes (Table 1 of the paper: STREAM copy and the
+ *      array-update loop a[i] += 1 of Sect. 2.3) ---------------------------
+ * n doubles, n even, 16-byte aligned device buffers; asynchronous. */
+int jacobi_probe_copy(const double *src, double *dst, int64_t n, void *stream);
+int jacobi_probe_update(double *a, int64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACOBI_H */

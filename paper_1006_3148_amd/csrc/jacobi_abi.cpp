@@ -1,0 +1,557 @@
+// Host runtime of libjacobi: descriptor validation, trip planning (how many
+// sweeps each launch fuses, tile shape, k segments), the compressed-grid
+// shift bookkeeping and the C-ABI entry points declared in include/jacobi.h.
+//
+// The paper's team sweep (Sect. 2.1) becomes one "trip": a launch that applies
+// t sweeps to the whole box with one read and one write of the grid.  n sweeps
+// are split into floor(n/t) trips of t plus one shorter trip; since every trip
+// computes exactly the plain sweeps, the split does not change a single bit.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "jacobi.h"
+#include "internal.h"
+
+using namespace jacobi_impl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(JACOBI_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int kCUs = 256;  // MI355X compute units
+
+struct Plan {
+    TripConfig cfg;
+    int tiles_x = 0, tiles_y = 0, segs = 0, seg_len = 0, ntiles = 0;
+};
+
+// Default tile shape per sweeps-per-trip (chosen so the per-stage register
+// state fits without spilling; see the trip kernel).
+TripConfig default_cfg(int T)
+{
+    if (T <= 2) return TripConfig{T, 4, 16};
+    return TripConfig{T, 4, 8};
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
+               int seg_req, bool compressed, Plan* out)
+{
+    const int T = cfg.T;
+    const int OX = 64 - 2 * T;
+    const int OY = cfg.R * cfg.W - 2 * T;
+    const int need = compressed ? 2 * T : 1;
+    if (OX < need || OY < need) return false;
+    Plan p;
+    p.cfg = cfg;
+    p.tiles_x = (int)((nx + 2 + OX - 1) / OX);
+    p.tiles_y = (int)((ny + 2 + OY - 1) / OY);
+    const int64_t nz2 = nz + 2;
+    const int64_t plane_tiles = (int64_t)p.tiles_x * p.tiles_y;
+    if (seg_req > 0) {
+        if (compressed && seg_req < 2 * T) return false;
+        p.seg_len = (int)std::min<int64_t>(seg_req, nz2);
+    } else {
+        // Minimise (rounds of concurrent tiles) x (planes each tile streams).
+        double best = 1e300;
+        int best_len = (int)nz2;
+        const int min_len = std::max(compressed ? 2 * T : 1, 4 * T);
+        for (int64_t segs = 1; segs <= 256; ++segs) {
+            const int64_t len = (nz2 + segs - 1) / segs;
+            if (len < min_len && segs > 1) break;
+            const int64_t real_segs = (nz2 + len - 1) / len;
+            const int64_t tiles = plane_tiles * real_segs;
+            const int64_t rounds = (tiles + kCUs - 1) / kCUs;
+            const double cost = (double)rounds * (double)(len + 1.5 * T);
+            if (cost < best * 0.999) {
+                best = cost;
+                best_len = (int)len;
+            }
+        }
+        p.seg_len = best_len;
+    }
+    p.segs = (int)((nz2 + p.seg_len - 1) / p.seg_len);
+    const int64_t nt = plane_tiles * p.segs;
+    if (nt > (1 << 30)) return false;
+    p.ntiles = (int)nt;
+    *out = p;
+    return true;
+}
+
+}  // namespace
+
+struct jacobi_s {
+    jacobi_desc d{};
+    int t = 4;
+    int64_t px = 0, py = 0;  // storage pitches of the FP64 grid(s)
+    int room = 0;            // compressed: shift room per axis
+    int off = 0;             // compressed: current origin offset per axis
+    int cur = 0;             // AB: grid holding the current iterate
+    hipStream_t stream = nullptr;
+    int tile_rows = 0, rpw = 0, seg_req = 0;
+    int inner = 32;
+    int64_t sweeps = 0;
+    int64_t spin_limit = 1 << 25;
+    Plan plans[9];           // plans[T] for T = 1..t
+    // workspace carve-up
+    char* ws = nullptr;
+    int* ticket = nullptr;
+    int* err = nullptr;
+    int* scale_exp = nullptr;
+    double* red_out = nullptr;
+    double* partials = nullptr;
+    int* flags = nullptr;
+    int64_t flag_ints = 0;
+    float* e[2] = {nullptr, nullptr};
+    float* rhs = nullptr;
+};
+
+namespace {
+
+struct Layout {
+    size_t partials_off, flags_off, e0_off, e1_off, rhs_off, total;
+    int64_t flag_ints;
+};
+
+int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
+                      Layout* lay)
+{
+    if (!d) return fail(JACOBI_EINVAL, "null descriptor");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return fail(JACOBI_EINVAL, "interior dims must be >= 1 (got %lld %lld %lld)",
+                    (long long)d->nx, (long long)d->ny, (long long)d->nz);
+    if (d->nx > 65536 || d->ny > 65536 || d->nz > 65536)
+        return fail(JACOBI_EINVAL, "interior dims must be <= 65536");
+    if (d->dtype != JACOBI_F64 && d->dtype != JACOBI_F32_REFINED)
+        return fail(JACOBI_EINVAL, "unknown dtype %d", d->dtype);
+    if (d->layout != JACOBI_LAYOUT_AB && d->layout != JACOBI_LAYOUT_COMPRESSED)
+        return fail(JACOBI_EINVAL, "unknown layout %d", d->layout);
+    const int t = d->t == 0 ? 4 : d->t;
+    if (t < 1 || t > 8)
+        return fail(JACOBI_EUNSUPPORTED,
+                    "sweeps per trip t=%d not supported (1..8)", t);
+    if (d->inner_sweeps < 0) return fail(JACOBI_EINVAL, "inner_sweeps < 0");
+    if (d->seg_len < 0) return fail(JACOBI_EINVAL, "seg_len < 0");
+    const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
+    const int room = comp ? t : 0;
+    const int64_t plane_bytes = (d->nx + 2 + room) * (d->ny + 2 + room) * 8;
+    if (plane_bytes >= ((int64_t)1 << 31))
+        return fail(JACOBI_EINVAL, "one k-plane must be < 2 GiB");
+    int64_t max_tiles = 0;
+    for (int T = 1; T <= t; ++T) {
+        TripConfig cfg = default_cfg(T);
+        if (T == t && (d->tile_rows > 0 || d->rows_per_wave > 0)) {
+            const int R = d->rows_per_wave > 0 ? d->rows_per_wave : 4;
+            const int rows = d->tile_rows > 0 ? d->tile_rows : cfg.R * cfg.W;
+            if (rows % R != 0)
+                return fail(JACOBI_EINVAL, "tile_rows must be a multiple of rows_per_wave");
+            cfg = TripConfig{T, R, rows / R};
+        }
+        if (!trip_config_supported(d->dtype == JACOBI_F32_REFINED, cfg))
+            return fail(JACOBI_EUNSUPPORTED,
+                        "tile shape t=%d rows=%d rows_per_wave=%d is not compiled",
+                        T, cfg.R * cfg.W, cfg.R);
+        if (!make_plan(d->nx, d->ny, d->nz, cfg, T == t ? d->seg_len : 0, comp,
+                       &plans[T]))
+            return fail(JACOBI_EUNSUPPORTED,
+                        "tile shape t=%d rows=%d cannot cover this box%s", T,
+                        cfg.R * cfg.W,
+                        comp ? " (compressed needs tiles and segments >= 2t)" : "");
+        max_tiles = std::max<int64_t>(max_tiles, plans[T].ntiles);
+    }
+    *t_out = t;
+    Layout L{};
+    const int nb = residual_blocks((int)d->nx, (int)d->ny, (int)d->nz);
+    L.partials_off = 256;
+    L.flags_off = (size_t)round_up(L.partials_off + 2 * nb * sizeof(double), 256);
+    L.flag_ints = comp ? max_tiles * kFlagStride : 0;
+    size_t end = (size_t)round_up(L.flags_off + L.flag_ints * sizeof(int), 256);
+    L.e0_off = L.e1_off = L.rhs_off = 0;
+    if (d->dtype == JACOBI_F32_REFINED) {
+        const int64_t box = (d->nx + 2) * (d->ny + 2) * (d->nz + 2);
+        const size_t fb = (size_t)round_up(box * (int64_t)sizeof(float), 256);
+        L.e0_off = end;
+        L.e1_off = end + fb;
+        L.rhs_off = end + 2 * fb;
+        end += 3 * fb;
+    }
+    L.total = end;
+    *lay = L;
+    return JACOBI_OK;
+}
+
+hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
+                       const float* rhs, int64_t px, int64_t py, int mode,
+                       int dir)
+{
+    const Plan& pl = h->plans[T];
+    TripParams p{};
+    p.src = src;
+    p.dst = dst;
+    p.rhs = rhs;
+    p.px = px;
+    p.py = py;
+    p.rpx = px;
+    p.rpy = py;
+    p.nx = (int)h->d.nx;
+    p.ny = (int)h->d.ny;
+    p.nz = (int)h->d.nz;
+    p.tiles_x = pl.tiles_x;
+    p.tiles_y = pl.tiles_y;
+    p.segs = pl.segs;
+    p.seg_len = pl.seg_len;
+    p.ntiles = pl.ntiles;
+    p.mode = mode;
+    p.dir = dir;
+    p.flags = h->flags;
+    p.ticket = h->ticket;
+    p.err = h->err;
+    p.spin_limit = h->spin_limit;
+    if (mode == 1) {
+        hipError_t e = launch_fill_i32(h->flags, 0, (int64_t)pl.ntiles * kFlagStride,
+                                       h->stream);
+        if (e != hipSuccess) return e;
+        e = launch_fill_i32(h->ticket, 0, 1, h->stream);
+        if (e != hipSuccess) return e;
+    }
+    return f32 ? launch_trip_f32(pl.cfg, p, h->stream)
+               : launch_trip_f64(pl.cfg, p, h->stream);
+}
+
+double* grid_origin(jacobi_t* h, int which_off)
+{
+    double* base = static_cast<double*>(h->d.grid0);
+    if (h->d.layout == JACOBI_LAYOUT_AB)
+        return static_cast<double*>(which_off == 0 ? h->d.grid0 : h->d.grid1);
+    return base + (int64_t)which_off * (1 + h->px + h->py);
+}
+
+double* current_origin(jacobi_t* h)
+{
+    if (h->d.layout == JACOBI_LAYOUT_AB) return grid_origin(h, h->cur);
+    return grid_origin(h, h->off);
+}
+
+// n FP64 sweeps of the u grid(s).
+int run_f64(jacobi_t* h, int64_t n)
+{
+    while (n > 0) {
+        int L = (int)std::min<int64_t>(h->t, n);
+        hipError_t e;
+        if (h->d.layout == JACOBI_LAYOUT_AB) {
+            e = launch_trip(h, L, false, grid_origin(h, h->cur),
+                            grid_origin(h, 1 - h->cur), nullptr, h->px, h->py,
+                            0, 1);
+            h->cur ^= 1;
+        } else {
+            int dir;
+            if (h->off >= L) {
+                dir = 1;
+            } else if (h->room - h->off >= L) {
+                dir = -1;
+            } else {
+                L = h->off;  // move back to offset 0 first
+                dir = 1;
+            }
+            const int noff = h->off - dir * L;
+            e = launch_trip(h, L, false, grid_origin(h, h->off),
+                            grid_origin(h, noff), nullptr, h->px, h->py, 1, dir);
+            h->off = noff;
+        }
+        if (e != hipSuccess) return hip_fail(e, "trip launch");
+        n -= L;
+        h->sweeps += L;
+    }
+    return JACOBI_OK;
+}
+
+// One outer step of the FP32-refined iteration with m inner sweeps.
+int outer_f32(jacobi_t* h, int64_t m)
+{
+    const int nx = (int)h->d.nx, ny = (int)h->d.ny, nz = (int)h->d.nz;
+    const int64_t epx = nx + 2, epy = (int64_t)(nx + 2) * (ny + 2);
+    double* u = current_origin(h);
+    hipError_t e = launch_residual(u, h->px, h->py, nx, ny, nz, h->partials,
+                                   h->red_out, h->stream);
+    if (e == hipSuccess)
+        e = launch_make_rhs(u, h->px, h->py, nx, ny, nz, h->red_out + 1,
+                            h->scale_exp, h->rhs, epx, epy, h->stream);
+    if (e == hipSuccess)
+        e = launch_fill_f32(h->e[0], 0.f, epy * (nz + 2), h->stream);
+    if (e != hipSuccess) return hip_fail(e, "refinement set-up");
+    int ce = 0;
+    int64_t left = m;
+    while (left > 0) {
+        const int L = (int)std::min<int64_t>(h->t, left);
+        e = launch_trip(h, L, true, h->e[ce], h->e[1 - ce], h->rhs, epx, epy, 0, 1);
+        if (e != hipSuccess) return hip_fail(e, "FP32 trip launch");
+        ce ^= 1;
+        left -= L;
+    }
+    e = launch_apply_correction(u, h->px, h->py, nx, ny, nz, h->e[ce], epx, epy,
+                                h->scale_exp, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "correction launch");
+    h->sweeps += m;
+    return JACOBI_OK;
+}
+
+int check_pending(jacobi_t* h)
+{
+    int errw = 0;
+    hipError_t e = hipMemcpyAsync(&errw, h->err, sizeof(int),
+                                  hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    if (errw != 0) {
+        launch_fill_i32(h->err, 0, 1, h->stream);
+        hipStreamSynchronize(h->stream);
+        return fail(JACOBI_ETIMEOUT,
+                    "a tile progress wait exceeded its spin bound; results of "
+                    "the affected sweeps are undefined");
+    }
+    return JACOBI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* jacobi_last_error(void) { return g_err.c_str(); }
+
+int jacobi_tile_supported(int32_t dtype, int32_t t, int32_t tile_rows,
+                          int32_t rows_per_wave)
+{
+    if (rows_per_wave <= 0 || tile_rows <= 0 || tile_rows % rows_per_wave) return 0;
+    return trip_config_supported(dtype == JACOBI_F32_REFINED,
+                                 TripConfig{t, rows_per_wave, tile_rows / rows_per_wave})
+               ? 1
+               : 0;
+}
+
+int jacobi_grid_bytes(const jacobi_desc* d, size_t* bytes)
+{
+    if (!d || !bytes) return fail(JACOBI_EINVAL, "null argument");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return fail(JACOBI_EINVAL, "interior dims must be >= 1");
+    const int t = d->t == 0 ? 4 : d->t;
+    const int room = d->layout == JACOBI_LAYOUT_COMPRESSED ? t : 0;
+    *bytes = (size_t)((d->nx + 2 + room) * (d->ny + 2 + room) * (d->nz + 2 + room) * 8);
+    return JACOBI_OK;
+}
+
+int jacobi_workspace_size(const jacobi_desc* d, size_t* bytes)
+{
+    if (!bytes) return fail(JACOBI_EINVAL, "null argument");
+    Plan plans[9];
+    int t = 0;
+    Layout L{};
+    int rc = validate_and_plan(d, plans, &t, &L);
+    if (rc != JACOBI_OK) return rc;
+    *bytes = L.total;
+    return JACOBI_OK;
+}
+
+int jacobi_create(const jacobi_desc* d, jacobi_t** out)
+{
+    if (!out) return fail(JACOBI_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    Plan plans[9];
+    int t = 0;
+    Layout L{};
+    int rc = validate_and_plan(d, plans, &t, &L);
+    if (rc != JACOBI_OK) return rc;
+    if (!d->grid0) return fail(JACOBI_EINVAL, "grid0 is null");
+    if (reinterpret_cast<uintptr_t>(d->grid0) % 16)
+        return fail(JACOBI_EINVAL, "grid0 must be 16-byte aligned");
+    if (d->layout == JACOBI_LAYOUT_AB) {
+        if (!d->grid1) return fail(JACOBI_EINVAL, "grid1 is null (AB layout)");
+        if (reinterpret_cast<uintptr_t>(d->grid1) % 16)
+            return fail(JACOBI_EINVAL, "grid1 must be 16-byte aligned");
+        if (d->grid1 == d->grid0) return fail(JACOBI_EINVAL, "grid1 == grid0");
+    }
+    if (!d->workspace || d->workspace_bytes < L.total)
+        return fail(JACOBI_EWORKSPACE, "workspace of %zu bytes needed, %zu given",
+                    L.total, d->workspace ? d->workspace_bytes : (size_t)0);
+    if (reinterpret_cast<uintptr_t>(d->workspace) % 256)
+        return fail(JACOBI_EINVAL, "workspace must be 256-byte aligned");
+
+    jacobi_t* h = new (std::nothrow) jacobi_s();
+    if (!h) return fail(JACOBI_EINVAL, "out of host memory");
+    h->d = *d;
+    h->t = t;
+    for (int T = 1; T <= t; ++T) h->plans[T] = plans[T];
+    const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
+    h->room = comp ? t : 0;
+    h->off = h->room;
+    h->px = d->nx + 2 + h->room;
+    h->py = h->px * (d->ny + 2 + h->room);
+    h->stream = static_cast<hipStream_t>(d->stream);
+    h->inner = d->inner_sweeps > 0 ? d->inner_sweeps : 32;
+    if (const char* s = std::getenv("JACOBI_SPIN_LIMIT")) {
+        long long v = std::atoll(s);
+        if (v > 0) h->spin_limit = v;
+    }
+    h->ws = static_cast<char*>(d->workspace);
+    h->ticket = reinterpret_cast<int*>(h->ws);
+    h->err = h->ticket + 1;
+    h->scale_exp = h->ticket + 2;
+    h->red_out = reinterpret_cast<double*>(h->ws + 64);
+    h->partials = reinterpret_cast<double*>(h->ws + L.partials_off);
+    h->flags = reinterpret_cast<int*>(h->ws + L.flags_off);
+    h->flag_ints = L.flag_ints;
+    if (d->dtype == JACOBI_F32_REFINED) {
+        h->e[0] = reinterpret_cast<float*>(h->ws + L.e0_off);
+        h->e[1] = reinterpret_cast<float*>(h->ws + L.e1_off);
+        h->rhs = reinterpret_cast<float*>(h->ws + L.rhs_off);
+    }
+    hipError_t e = launch_fill_i32(h->ticket, 0, 16, h->stream);
+    if (e == hipSuccess && d->layout == JACOBI_LAYOUT_AB) {
+        const int nx2 = (int)d->nx + 2, ny2 = (int)d->ny + 2, nz2 = (int)d->nz + 2;
+        e = launch_copy_box_f64(static_cast<const double*>(d->grid0), h->px, h->py,
+                                static_cast<double*>(d->grid1), h->px, h->py, nx2,
+                                ny2, nz2, h->stream);
+    }
+    if (e == hipSuccess && d->dtype == JACOBI_F32_REFINED) {
+        const int64_t box = (d->nx + 2) * (d->ny + 2) * (d->nz + 2);
+        e = launch_fill_f32(h->e[0], 0.f, box, h->stream);
+        if (e == hipSuccess) e = launch_fill_f32(h->e[1], 0.f, box, h->stream);
+        if (e == hipSuccess) e = launch_fill_f32(h->rhs, 0.f, box, h->stream);
+    }
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "set-up launch");
+    }
+    *out = h;
+    return JACOBI_OK;
+}
+
+int jacobi_sweep(jacobi_t* h, int64_t n_steps)
+{
+    if (!h) return fail(JACOBI_EINVAL, "null handle");
+    if (n_steps < 0) return fail(JACOBI_EINVAL, "n_steps < 0");
+    if (h->d.dtype == JACOBI_F64) return run_f64(h, n_steps);
+    while (n_steps > 0) {
+        const int64_t m = std::min<int64_t>(h->inner, n_steps);
+        int rc = outer_f32(h, m);
+        if (rc != JACOBI_OK) return rc;
+        n_steps -= m;
+    }
+    return JACOBI_OK;
+}
+
+int jacobi_residual(jacobi_t* h, double* l2, double* maxabs)
+{
+    if (!h || !l2) return fail(JACOBI_EINVAL, "null argument");
+    hipError_t e = launch_residual(current_origin(h), h->px, h->py, (int)h->d.nx,
+                                   (int)h->d.ny, (int)h->d.nz, h->partials,
+                                   h->red_out, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual launch");
+    double out[2] = {0, 0};
+    e = hipMemcpyAsync(out, h->red_out, sizeof out, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual copy");
+    int rc = check_pending(h);
+    if (rc != JACOBI_OK) return rc;
+    *l2 = out[0];
+    if (maxabs) *maxabs = out[1];
+    return JACOBI_OK;
+}
+
+int jacobi_solve(jacobi_t* h, double rel_tol, double r0, int64_t max_sweeps,
+                 int64_t check_every, int64_t* sweeps_done, double* final_l2)
+{
+    if (!h) return fail(JACOBI_EINVAL, "null handle");
+    if (!(rel_tol > 0) || max_sweeps < 0 || check_every < 1)
+        return fail(JACOBI_EINVAL, "need rel_tol > 0, max_sweeps >= 0, check_every >= 1");
+    double r = 0;
+    int rc = jacobi_residual(h, &r, nullptr);
+    if (rc != JACOBI_OK) return rc;
+    if (!(r0 > 0)) r0 = r;
+    int64_t done = 0;
+    while (r > rel_tol * r0 && done < max_sweeps) {
+        const int64_t m = std::min(check_every, max_sweeps - done);
+        rc = jacobi_sweep(h, m);
+        if (rc != JACOBI_OK) return rc;
+        done += m;
+        rc = jacobi_residual(h, &r, nullptr);
+        if (rc != JACOBI_OK) return rc;
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (final_l2) *final_l2 = r;
+    return JACOBI_OK;
+}
+
+int jacobi_sync(jacobi_t* h)
+{
+    if (!h) return fail(JACOBI_EINVAL, "null handle");
+    return check_pending(h);
+}
+
+int jacobi_current(jacobi_t* h, void** origin, int64_t strides[3])
+{
+    if (!h || !origin || !strides) return fail(JACOBI_EINVAL, "null argument");
+    *origin = current_origin(h);
+    strides[0] = 1;
+    strides[1] = h->px;
+    strides[2] = h->py;
+    return JACOBI_OK;
+}
+
+int jacobi_info(jacobi_t* h, int64_t* sweeps_done, int32_t* t,
+                int32_t* tile_rows, int32_t* seg_len)
+{
+    if (!h) return fail(JACOBI_EINVAL, "null handle");
+    if (sweeps_done) *sweeps_done = h->sweeps;
+    if (t) *t = h->t;
+    if (tile_rows) *tile_rows = h->plans[h->t].cfg.R * h->plans[h->t].cfg.W;
+    if (seg_len) *seg_len = h->plans[h->t].seg_len;
+    return JACOBI_OK;
+}
+
+int jacobi_destroy(jacobi_t* h)
+{
+    delete h;
+    return JACOBI_OK;
+}
+
+int jacobi_probe_copy(const double* src, double* dst, int64_t n, void* stream)
+{
+    if (!src || !dst || n < 2 || (n & 1) ||
+        (reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16)
+        return fail(JACOBI_EINVAL, "probe needs even n >= 2 and 16-byte aligned buffers");
+    hipError_t e = launch_stream_copy(src, dst, n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JACOBI_OK : hip_fail(e, "copy probe");
+}
+
+int jacobi_probe_update(double* a, int64_t n, void* stream)
+{
+    if (!a || n < 2 || (n & 1) || reinterpret_cast<uintptr_t>(a) % 16)
+        return fail(JACOBI_EINVAL, "probe needs even n >= 2 and a 16-byte aligned buffer");
+    hipError_t e = launch_stream_update(a, n, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JACOBI_OK : hip_fail(e, "update probe");
+}
+
+}  // extern "C"

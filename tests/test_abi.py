@@ -1,0 +1,113 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/jacobi.h declares, and rejects bad descriptors with negative
+status codes (validation happens before any HIP call)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "jacobi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(jacobi_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1006_3148_amd as pkg
+    names = _declared()
+    assert "jacobi_create" in names and "jacobi_sweep" in names
+    for n in names:
+        assert hasattr(pkg.lib, n), n
+    assert set(names) == set(pkg._lib.EXPORTED)
+
+
+def _desc(**kw):
+    from paper_1006_3148_amd._lib import JacobiDesc
+    d = JacobiDesc()
+    d.nx, d.ny, d.nz = kw.pop("dims", (8, 8, 8))
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def _rc(fn, *args):
+    return fn(*args)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dims=(0, 8, 8)), -1),
+    (dict(dims=(8, -1, 8)), -1),
+    (dict(dims=(70000, 8, 8)), -1),
+    (dict(dtype=7), -1),
+    (dict(layout=3), -1),
+    (dict(t=9), -2),
+    (dict(t=-1), -2),
+    (dict(inner_sweeps=-3), -1),
+    (dict(tile_rows=33, rows_per_wave=4), -1),
+    (dict(tile_rows=24, rows_per_wave=4), -2),
+])
+def test_bad_descriptors_are_rejected(kw, code):
+    from paper_1006_3148_amd import lib
+    d = _desc(**kw)
+    n = ctypes.c_size_t()
+    assert lib.jacobi_workspace_size(ctypes.byref(d), ctypes.byref(n)) == code
+    h = ctypes.c_void_p()
+    assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == code
+    assert h.value is None
+    assert lib.jacobi_last_error().decode() != ""
+
+
+def test_create_checks_buffers_before_touching_the_gpu():
+    from paper_1006_3148_amd import lib
+    d = _desc()
+    h = ctypes.c_void_p()
+    assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == -1  # grid0 null
+    d.grid0 = 4096
+    assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == -1  # grid1 null
+    d.grid1 = 4096
+    assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == -1  # same grid
+    d.grid1 = 8192 + 8
+    assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == -1  # misaligned
+    d.grid1 = 8192
+    assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == -3  # workspace
+    d.workspace = 1 << 20
+    d.workspace_bytes = 16
+    assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == -3
+    assert lib.jacobi_create(ctypes.byref(d), None) == -1
+
+
+def test_sizes():
+    from paper_1006_3148_amd import lib
+    d = _desc(dims=(10, 6, 4))
+    n = ctypes.c_size_t()
+    assert lib.jacobi_grid_bytes(ctypes.byref(d), ctypes.byref(n)) == 0
+    assert n.value == 12 * 8 * 6 * 8
+    d.layout = 1
+    d.t = 3
+    assert lib.jacobi_grid_bytes(ctypes.byref(d), ctypes.byref(n)) == 0
+    assert n.value == 15 * 11 * 9 * 8
+    d.dtype = 1
+    assert lib.jacobi_workspace_size(ctypes.byref(d), ctypes.byref(n)) == 0
+    assert n.value >= 3 * 12 * 8 * 6 * 4
+
+
+def test_null_handle_calls_fail_cleanly():
+    from paper_1006_3148_amd import lib
+    assert lib.jacobi_sweep(None, 1) == -1
+    l2 = ctypes.c_double()
+    assert lib.jacobi_residual(None, ctypes.byref(l2), None) == -1
+    assert lib.jacobi_sync(None) == -1
+    assert lib.jacobi_destroy(None) == 0
+
+
+def test_tile_menu():
+    from paper_1006_3148_amd import tile_supported
+    assert tile_supported(1, 64, 4)
+    assert tile_supported(4, 32, 4)
+    assert not tile_supported(4, 24, 4)
+    assert not tile_supported(9, 32, 4)

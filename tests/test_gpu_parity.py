@@ -1,0 +1,116 @@
+"""GPU parity of the HIP trip kernels against the CPU oracle (bitwise FP64).
+
+Sizes span several tiles in i and j, several k segments and ragged tails;
+degenerate boxes (1-cell dims) and sweep counts that are not multiples of t
+(remainder trips) are included.  Every case prints its name before running.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _bits(a):
+    return a.view(np.uint64)
+
+
+def _run(box, n, **kw):
+    from paper_1006_3148_amd import Jacobi
+    j = Jacobi(box, **kw)
+    j.sweep(n)
+    out = j.box()
+    info = j.info()
+    j.close()
+    return out, info
+
+
+def _assert_same(got, want, what):
+    if not np.array_equal(_bits(got), _bits(want)):
+        diff = np.argwhere(got != want)
+        raise AssertionError("%s: %d cells differ, first at (k,j,i)=%s: got %r "
+                             "want %r" % (what, len(diff), tuple(diff[0]),
+                                          got[tuple(diff[0])], want[tuple(diff[0])]))
+
+
+DIMS = [(70, 45, 37), (1, 1, 1), (3, 2, 5), (130, 67, 21), (64, 64, 64)]
+
+
+@pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("dims", DIMS)
+def test_ab_trips_bitwise(t, dims):
+    nx, ny, nz = dims
+    box = synth.uniform_box(nx, ny, nz, seed=100 + t)
+    n = 2 * t + 1
+    print("case ab t=%d dims=%s n=%d" % (t, dims, n), flush=True)
+    want = oracle.sweeps_f64(box, n)
+    got, _ = _run(box, n, t=t, layout="ab")
+    _assert_same(got, want, "ab t=%d %s" % (t, dims))
+
+
+@pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("dims", [(70, 45, 37), (2, 3, 1), (130, 67, 40)])
+def test_compressed_trips_bitwise(t, dims):
+    nx, ny, nz = dims
+    box = synth.uniform_box(nx, ny, nz, seed=200 + t)
+    # 3t+2 sweeps: forward and backward trips plus a short trip that brings the
+    # shift offset back before a full backward trip.
+    n = 3 * t + 2
+    print("case compressed t=%d dims=%s n=%d" % (t, dims, n), flush=True)
+    want = oracle.sweeps_f64(box, n)
+    got, _ = _run(box, n, t=t, layout="compressed")
+    _assert_same(got, want, "compressed t=%d %s" % (t, dims))
+
+
+def test_single_sweep_config_64cube_100_sweeps():
+    box = synth.uniform_box(64, 64, 64, seed=1)
+    print("case 64^3 x 100, t=1", flush=True)
+    want = oracle.sweeps_f64(box, 100)
+    got, _ = _run(box, 100, t=1, layout="ab")
+    _assert_same(got, want, "64^3 t=1")
+
+
+def test_residual_matches_oracle_and_is_deterministic():
+    from paper_1006_3148_amd import Jacobi
+    box = synth.uniform_box(90, 70, 50, seed=7)
+    print("case residual 90x70x50", flush=True)
+    j = Jacobi(box, t=4)
+    j.sweep(9)
+    r1, m1 = j.residual()
+    r2, m2 = j.residual()
+    u = j.box()
+    j.close()
+    assert r1 == r2 and m1 == m2
+    ro = oracle.residual_norm(u)
+    assert abs(r1 - ro) <= 1e-12 * ro
+    assert m1 == float(np.max(np.abs(oracle.residual_f64(u))))
+
+
+@pytest.mark.parametrize("layout", ["ab", "compressed"])
+def test_split_of_sweeps_does_not_change_bits(layout):
+    from paper_1006_3148_amd import Jacobi
+    box = synth.uniform_box(50, 41, 33, seed=9)
+    print("case split", layout, flush=True)
+    j = Jacobi(box, t=4, layout=layout)
+    for n in (1, 5, 3, 4, 2):
+        j.sweep(n)
+    got = j.box()
+    j.close()
+    _assert_same(got, oracle.sweeps_f64(box, 15), "split " + layout)
+
+
+@pytest.mark.parametrize("layout", ["ab", "compressed"])
+def test_f32_refined_matches_oracle(layout):
+    from paper_1006_3148_amd import Jacobi
+    box = synth.uniform_box(40, 33, 29, seed=12)
+    m_in, outer = 6, 3
+    print("case f32 refined", layout, flush=True)
+    want = oracle.refine_f32(box, m_in, outer)
+    j = Jacobi(box, t=4, layout=layout, dtype="f32_refined", inner_sweeps=m_in)
+    j.sweep(m_in * outer)
+    got = j.box()
+    j.close()
+    _assert_same(got, want, "f32 refined " + layout)
