@@ -1,0 +1,257 @@
+"""Benchmark of the temporally blocked FP64 3D 7-point Jacobi hot path.
+
+One "step" = 200 FP64 Jacobi sweeps of a 512^3 interior (514^3 box, Dirichlet
+boundary U[0,1) from seed 2, interior 0) through the trip kernel, followed by
+one residual-norm check -- the workload the headline metric is quoted on.
+
+Prints ONE JSON line (rank 0) with GLUP/s (interior cells x sweeps / s / 1e9),
+the roofline of the dominant kernel (the trip kernel, HBM-bound: algorithmic
+16 B per interior cell per trip) measured with HIP events on the solver's
+stream, and the CPU oracle timed on a bounded sample on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--t T]
+                       [--layout ab|compressed] [--no-extra] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512, help="interior edge length")
+    ap.add_argument("--sweeps", type=int, default=200, help="sweeps per step")
+    ap.add_argument("--t", type=int, default=0, help="sweeps per trip (0=best)")
+    ap.add_argument("--layout", default="", help="ab | compressed ('' = best)")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--probe", action="store_true",
+                    help="only run the copy probe (1 GiB in, 1 GiB out) 5 times; "
+                         "used to scale HBM byte counters")
+    return ap.parse_args()
+
+
+# Default configuration of the headline line; chosen from the measured sweep
+# over t and layouts (the "extra" block reproduces that sweep on every run).
+DEFAULT_T = 3
+DEFAULT_LAYOUT = "ab"
+
+
+def time_steps(j, steps, sweeps, t, torch):
+    """Time `steps` steps; per-trip HIP events give the trip-kernel duration."""
+    stream = j.stream
+    trips_per_step = []
+    left = sweeps
+    while left > 0:
+        trips_per_step.append(min(t, left))
+        left -= trips_per_step[-1]
+    full = [L for L in trips_per_step if L == t]
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        for L in trips_per_step:
+            if L == t:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                j.sweep(L)
+                b.record(stream)
+                ev.append((a, b))
+            else:
+                j.sweep(L)
+        j.residual()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = start.elapsed_time(end)
+    trip_ms = [a.elapsed_time(b) for a, b in ev]
+    j.sync()
+    return wall, gpu_ms, trip_ms, len(full)
+
+
+def cpu_baseline(n, seconds):
+    import numpy as np
+    import oracle
+    import synth
+    box = synth.uniform_box(n, n, n, seed=2)
+    nt = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.sweeps_f64(box, 1, nthreads=nt)
+    one = time.perf_counter() - t0
+    s = max(1, int(seconds / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.sweeps_f64(box, s, nthreads=nt)
+    dt = time.perf_counter() - t0
+    del np
+    return {"value": round(n ** 3 * s / dt / 1e9, 4), "unit": "GLUP/s",
+            "cores": nt, "kind": "oracle",
+            "sample": "%d^3 interior, %d FP64 sweeps of the plain C oracle "
+                      "(OpenMP over k planes, %d threads), %.1f s" % (n, s, nt, dt)}
+
+
+def glups(n, sweeps, seconds):
+    return n ** 3 * sweeps / seconds / 1e9
+
+
+def run_config(n, sweeps, t, layout, steps, warmup, torch, synth_box):
+    from paper_1006_3148_amd import Jacobi
+    j = Jacobi(synth_box, t=t, layout=layout)
+    for _ in range(warmup):
+        j.sweep(sweeps)
+    j.sync()
+    wall, gpu_ms, trip_ms, _ = time_steps(j, steps, sweeps, t, torch)
+    info = j.info()
+    j.close()
+    return wall, gpu_ms, trip_ms, info
+
+
+def probe_bw(torch, nbytes=2 << 30, reps=10):
+    from paper_1006_3148_amd import probe_copy, probe_update
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    probe_copy(a, b)
+    probe_update(a)
+    torch.cuda.synchronize()
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        probe_copy(a, b)
+    e.record()
+    torch.cuda.synchronize()
+    copy = 2 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+    s.record()
+    for _ in range(reps):
+        probe_update(a)
+    e.record()
+    torch.cuda.synchronize()
+    upd = 2 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return copy, upd
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; "
+                          "--gpus %d is not supported" % args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.probe:
+        from paper_1006_3148_amd import probe_copy
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            probe_copy(a, b)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read": a.numel() * 8,
+                          "bytes_written": b.numel() * 8, "launches": 5}))
+        return
+    n, sweeps = args.n, args.sweeps
+    t = args.t or DEFAULT_T
+    layout = args.layout or DEFAULT_LAYOUT
+    box = synth.uniform_box(n, n, n, seed=2)
+
+    wall, gpu_ms, trip_ms, info = run_config(n, sweeps, t, layout, args.steps,
+                                             args.warmup, torch, box)
+    value = glups(n, sweeps * args.steps, wall)
+    trip_avg_ms = float(np.mean(trip_ms))
+    alg_bytes = 16.0 * n ** 3  # one read + one write per interior cell per trip
+    achieved = alg_bytes / (trip_avg_ms * 1e-3) / 1e9
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "trip_kernel_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            tr = json.load(f)
+        if tr.get("kernel_config") == {"t": t, "layout": layout, "n": n} and \
+                tr.get("source_hash") == _kernel_hash():
+            traffic = tr.get("bytes_per_launch")
+
+    out = {
+        "metric": "GLUP/s FP64 7-pt Jacobi 512^3 (200 sweeps/step), "
+                  "temporally blocked",
+        "value": round(value, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: boundary U[0,1) seed 2, interior 0",
+        "config": {"workload": "%d^3 interior FP64 Jacobi, %d sweeps + 1 "
+                               "residual per step" % (n, sweeps),
+                   "t": t, "layout": layout, "tile_rows": info["tile_rows"],
+                   "seg_len": info["seg_len"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "trip_kernel<double,T=%d>" % t,
+                     "launch_ms": round(trip_avg_ms, 4),
+                     "alg_bytes_per_launch": alg_bytes},
+        "gpu_event_ms_per_step": round(gpu_ms / args.steps, 4),
+    }
+
+    if not args.no_extra:
+        extra = {}
+        copy_bw, upd_bw = probe_bw(torch)
+        extra["copy_probe_GBs"] = round(copy_bw, 1)
+        extra["update_probe_GBs"] = round(upd_bw, 1)
+        extra["roofline_glups_t1_spec"] = HBM_PEAK_GBS / 16.0
+        extra["roofline_glups_t1_copy"] = round(copy_bw / 16.0, 1)
+        tab = {}
+        for lay in ("ab", "compressed"):
+            for tt in range(1, 9):
+                w, _, tm, _ = run_config(n, sweeps, tt, lay, 1, 1, torch, box)
+                tab["%s_t%d" % (lay, tt)] = round(glups(n, sweeps, w), 1)
+        extra["glups_by_layout_t_512"] = tab
+        out["extra"] = extra
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def _kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels_trip.hip",):
+        with open(os.path.join(ROOT, "paper_1006_3148_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -53,7 +53,8 @@ struct Plan {
 TripConfig default_cfg(int T)
 {
     if (T <= 2) return TripConfig{T, 4, 16};
-    return TripConfig{T, 4, 8};
+    if (T <= 6) return TripConfig{T, 4, 8};
+    return TripConfig{T, 2, 16};
 }
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }

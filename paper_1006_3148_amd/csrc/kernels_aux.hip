@@ -159,22 +159,41 @@ __global__ __launch_bounds__(256) void copy_box_kernel(
     }
 }
 
-// 16 bytes per lane per access.
+// 16 bytes per lane per access, four independent accesses in flight per
+// lane per iteration.
 __global__ __launch_bounds__(256) void stream_copy_kernel(
     const double2* __restrict__ a, double2* __restrict__ b, int64_t n2)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n2;
-         x += stride)
-        b[x] = a[x];
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; x + 3 * stride < n2; x += 4 * stride) {
+        const double2 v0 = a[x], v1 = a[x + stride], v2 = a[x + 2 * stride],
+                      v3 = a[x + 3 * stride];
+        b[x] = v0;
+        b[x + stride] = v1;
+        b[x + 2 * stride] = v2;
+        b[x + 3 * stride] = v3;
+    }
+    for (; x < n2; x += stride) b[x] = a[x];
 }
 
 __global__ __launch_bounds__(256) void stream_update_kernel(
     double2* __restrict__ a, int64_t n2)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n2;
-         x += stride) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; x + 3 * stride < n2; x += 4 * stride) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = a[x + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u].x = v[u].x + 1.0;
+            v[u].y = v[u].y + 1.0;
+            a[x + u * stride] = v[u];
+        }
+    }
+    for (; x < n2; x += stride) {
         double2 v = a[x];
         v.x = v.x + 1.0;
         v.y = v.y + 1.0;
@@ -268,7 +287,7 @@ hipError_t launch_stream_copy(const double* a, double* b, int64_t n,
                               hipStream_t s)
 {
     const int64_t n2 = n / 2;
-    hipLaunchKernelGGL(stream_copy_kernel, dim3(grid_for_elems(n2 / 4)),
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(grid_for_elems(n2 / 8)),
                        dim3(256), 0, s, reinterpret_cast<const double2*>(a),
                        reinterpret_cast<double2*>(b), n2);
     return hipGetLastError();
@@ -277,7 +296,7 @@ hipError_t launch_stream_copy(const double* a, double* b, int64_t n,
 hipError_t launch_stream_update(double* a, int64_t n, hipStream_t s)
 {
     const int64_t n2 = n / 2;
-    hipLaunchKernelGGL(stream_update_kernel, dim3(grid_for_elems(n2 / 4)),
+    hipLaunchKernelGGL(stream_update_kernel, dim3(grid_for_elems(n2 / 8)),
                        dim3(256), 0, s, reinterpret_cast<double2*>(a), n2);
     return hipGetLastError();
 }

@@ -38,6 +38,8 @@
 // Compiled with -ffp-contract=off: no fused multiply-add, so results are
 // bitwise equal to the plain definition.
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace jacobi_impl {
@@ -106,7 +108,13 @@ __device__ __forceinline__ void flag_store(int* f, int v)
 
 constexpr int kDone = 0x7fffffff;
 
-template <typename Real, int T, int R, int W, bool RHS, bool FLAGS, bool EDGE>
+// Planes in flight per tile (register ring depth).
+#ifndef JACOBI_PREFETCH
+#define JACOBI_PREFETCH 3
+#endif
+constexpr int kPrefetch = JACOBI_PREFETCH;
+
+template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE>
 __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
                                          Real (*xch)[W][2][64])
 {
@@ -184,13 +192,10 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
             C[s][r] = Real(0);
         }
     float rq[RHS ? T : 1][R];
-    float rnext[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        rnext[r] = 0.f;
+    for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int s = 0; s < (RHS ? T : 1); ++s) rq[s][r] = 0.f;
-    }
 
     // Addressing: a scalar (per-plane) base plus a 32-bit per-row byte offset
     // that is loop invariant; src, dst and rhs frames share the pitches.
@@ -204,99 +209,124 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
     char* dst_b = reinterpret_cast<char*>(dst);
     const int64_t rplane_bytes = p.rpy * (int64_t)sizeof(float);
 
-    // Prefetch of the first plane (stage-1 input) and the first rhs plane.
-    Real nxt[R];
-    {
-        const char* sp = src_b + (int64_t)a * plane_bytes;
+    // Register ring of the next PF input planes (and rhs planes): plane
+    // loads are issued PF steps before use, so each step does not wait for a
+    // full memory round trip.
+    Real ring[PF][R];
+    float rring[RHS ? PF : 1][R];
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        const int q = a + d;
+        const char* sp = src_b + (int64_t)q * plane_bytes;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            nxt[r] = Real(0);
-            if (!EDGE || (lane_box && row_box[r]))
-                nxt[r] = *reinterpret_cast<const Real*>(sp + voff[r]);
+            ring[d][r] = Real(0);
+            if (q <= b && (!EDGE || (lane_box && row_box[r])))
+                ring[d][r] = *reinterpret_cast<const Real*>(sp + voff[r]);
         }
-    }
-    if (RHS) {
-        const int qr = a - 1;  // rhs plane stage 1 uses at step 0
-        if (qr >= 1 && qr <= p.nz) {
+        if (RHS) {
+            const int qr = a - 1 + d;  // rhs plane stage 1 uses at step d
             const char* rp = rhs_b + (int64_t)qr * rplane_bytes;
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (!EDGE || (lane_box && row_box[r]))
-                    rnext[r] = *reinterpret_cast<const float*>(rp + voff[r] / (sizeof(Real) / sizeof(float)));
+            for (int r = 0; r < R; ++r) {
+                rring[RHS ? d : 0][r] = 0.f;
+                if (qr >= 1 && qr <= p.nz && (!EDGE || (lane_box && row_box[r])))
+                    rring[RHS ? d : 0][r] = *reinterpret_cast<const float*>(
+                        rp + voff[r] / (sizeof(Real) / sizeof(float)));
+            }
         }
     }
 
     int phase = 0;
+#pragma unroll 2
     for (int n = 0; n < nsteps; ++n) {
         Real x[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = nxt[r];
+        for (int r = 0; r < R; ++r) x[r] = ring[0][r];
         if (RHS) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) rq[0][r] = rnext[r];
+            for (int r = 0; r < R; ++r) rq[0][r] = rring[0][r];
         }
-        // Issue next plane loads before the stage work.
-        const int qn = a + n + 1;
 #pragma unroll
-        for (int r = 0; r < R; ++r) nxt[r] = Real(0);
+        for (int d = 0; d + 1 < PF; ++d)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ring[d][r] = ring[d + 1][r];
+                if (RHS) rring[RHS ? d : 0][r] = rring[RHS ? d + 1 : 0][r];
+            }
+        // Issue the loads of plane a+n+PF (used PF steps from now).
+        const int qn = a + n + PF;
+#pragma unroll
+        for (int r = 0; r < R; ++r) ring[PF - 1][r] = Real(0);
         if (qn <= b) {
             const char* sp = src_b + (int64_t)qn * plane_bytes;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (!EDGE || (lane_box && row_box[r]))
-                    nxt[r] = *reinterpret_cast<const Real*>(sp + voff[r]);
+                    ring[PF - 1][r] = *reinterpret_cast<const Real*>(sp + voff[r]);
         }
         if (RHS) {
-            const int qr = a + n;  // rhs plane stage 1 uses at step n+1
+            const int qr = a + n + PF - 1;  // rhs plane stage 1 uses at step n+PF
 #pragma unroll
-            for (int r = 0; r < R; ++r) rnext[r] = 0.f;
+            for (int r = 0; r < R; ++r) rring[RHS ? PF - 1 : 0][r] = 0.f;
             if (qr >= 1 && qr <= p.nz) {
                 const char* rp = rhs_b + (int64_t)qr * rplane_bytes;
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (!EDGE || (lane_box && row_box[r]))
-                        rnext[r] = *reinterpret_cast<const float*>(rp + voff[r] / (sizeof(Real) / sizeof(float)));
+                        rring[RHS ? PF - 1 : 0][r] = *reinterpret_cast<const float*>(
+                            rp + voff[r] / (sizeof(Real) / sizeof(float)));
             }
         }
 
+        // The T stages of this step.  Only the first and last steps of a tile
+        // see the boundary planes 0 and nz+1 (pass-through); the common steps
+        // take the branch-free variant.
+        auto stages = [&](auto bnd_tag) {
+            constexpr bool BND = decltype(bnd_tag)::value;
 #pragma unroll
-        for (int s = 0; s < T; ++s) {
-            const int q = a + n - s;  // plane arriving at stage s+1
-            const int pe = q - 1;     // plane stage s+1 completes now
-            Real(*buf)[2][64] = xch[phase & 1];
-            ++phase;
-            buf[wave][0][lane] = x[0];
-            buf[wave][1][lane] = x[R - 1];
-            __syncthreads();
-            if (FLAGS && s == 0 && threadIdx.x == 0) {
-                // every wave has finished step n-1, so plane a+n-1 is consumed
-                flag_store(p.flags + (int64_t)tile * kFlagStride, a + n);
-            }
-            const Real up = buf[wave > 0 ? wave - 1 : 0][1][lane];
-            const Real dn = buf[wave < W - 1 ? wave + 1 : W - 1][0][lane];
-            const bool bnd = (pe == 0) || (pe == p.nz + 1);
-            // Row by row; `above` keeps the old value of row r-1.
-            Real above = up;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const Real xo = x[r];
-                const Real below = (r == R - 1) ? dn : x[r < R - 1 ? r + 1 : 0];
-                const Real inpl = ((from_left(xo) + from_right(xo)) + above) + below;
-                Real e;
-                if (bnd) {
-                    e = C[s][r];
-                } else {
-                    Real sum = P[s][r] + xo;
-                    if (RHS) sum = sum + (Real)rq[RHS ? s : 0][r];
-                    e = sum * c6;
-                    if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
+            for (int s = 0; s < T; ++s) {
+                const int q = a + n - s;  // plane arriving at stage s+1
+                const int pe = q - 1;     // plane stage s+1 completes now
+                Real(*buf)[2][64] = xch[phase & 1];
+                ++phase;
+                buf[wave][0][lane] = x[0];
+                buf[wave][1][lane] = x[R - 1];
+                __syncthreads();
+                if (FLAGS && s == 0 && threadIdx.x == 0) {
+                    // every wave has finished step n-1: plane a+n-1 is consumed
+                    flag_store(p.flags + (int64_t)tile * kFlagStride, a + n);
                 }
-                P[s][r] = inpl + C[s][r];
-                C[s][r] = xo;
-                x[r] = e;
-                above = xo;
+                const Real up = buf[wave > 0 ? wave - 1 : 0][1][lane];
+                const Real dn = buf[wave < W - 1 ? wave + 1 : W - 1][0][lane];
+                const bool bnd = BND && ((pe == 0) || (pe == p.nz + 1));
+                // Row by row; `above` keeps the old value of row r-1.
+                Real above = up;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const Real xo = x[r];
+                    const Real below = (r == R - 1) ? dn : x[r < R - 1 ? r + 1 : 0];
+                    const Real inpl = ((from_left(xo) + from_right(xo)) + above) + below;
+                    Real e;
+                    if (bnd) {
+                        e = C[s][r];
+                    } else {
+                        Real sum = P[s][r] + xo;
+                        if (RHS) sum = sum + (Real)rq[RHS ? s : 0][r];
+                        e = sum * c6;
+                        if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
+                    }
+                    P[s][r] = inpl + C[s][r];
+                    C[s][r] = xo;
+                    x[r] = e;
+                    above = xo;
+                }
             }
-        }
+        };
+        if (a + n - T <= 0 || a + n - 1 >= p.nz + 1)
+            stages(std::true_type{});
+        else
+            stages(std::false_type{});
         if (RHS) {
 #pragma unroll
             for (int s = (RHS ? T : 1) - 1; s > 0; --s)
@@ -349,7 +379,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
     }
 }
 
-template <typename Real, int T, int R, int W, bool RHS, bool FLAGS>
+template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS>
 __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 {
     constexpr int H = R * W;
@@ -377,18 +407,18 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
         const bool interior_tile = ilo >= 1 && ilo + 63 <= p.nx && jlo >= 1 &&
                                    jlo + H - 1 <= p.ny;
         if (interior_tile)
-            run_tile<Real, T, R, W, RHS, FLAGS, false>(p, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, false>(p, tile, xch);
         else
-            run_tile<Real, T, R, W, RHS, FLAGS, true>(p, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, true>(p, tile, xch);
     }
 }
 
-template <typename Real, int T, int R, int W, bool RHS>
+template <typename Real, int T, int R, int W, int PF, bool RHS>
 hipError_t launch_cfg(const TripParams& p, hipStream_t s)
 {
     dim3 block(64 * W);
     if (p.mode == 0) {
-        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, RHS, false>),
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, false>),
                            dim3(p.ntiles), block, 0, s, p);
     } else {
         int dev = 0, cus = 0;
@@ -397,11 +427,11 @@ hipError_t launch_cfg(const TripParams& p, hipStream_t s)
         int per_cu = 0;
         hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, reinterpret_cast<const void*>(
-                         &trip_kernel<Real, T, R, W, RHS, true>),
+                         &trip_kernel<Real, T, R, W, PF, RHS, true>),
             64 * W, 0);
         int grid = cus * (per_cu > 0 ? per_cu : 1);
         if (grid > p.ntiles) grid = p.ntiles;
-        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, RHS, true>), dim3(grid),
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, true>), dim3(grid),
                            block, 0, s, p);
     }
     return hipGetLastError();
@@ -420,7 +450,7 @@ template <typename Real, bool RHS>
 hipError_t dispatch(const TripConfig& c, const TripParams& p, hipStream_t s)
 {
 #define JACOBI_CASE(T_, R_, W_) \
-    if (c.T == T_ && c.R == R_ && c.W == W_) return launch_cfg<Real, T_, R_, W_, RHS>(p, s);
+    if (c.T == T_ && c.R == R_ && c.W == W_) return launch_cfg<Real, T_, R_, W_, kPrefetch, RHS>(p, s);
     JACOBI_TRIP_CFGS(JACOBI_CASE)
 #undef JACOBI_CASE
     return hipErrorInvalidValue;
