@@ -146,6 +146,58 @@ const char *jacobi_last_error(void);
 int jacobi_tile_supported(int32_t dtype, int32_t t, int32_t tile_rows,
                           int32_t rows_per_wave);
 
+/* ---- batched problems ---------------------------------------------------
+ * Many independent problems of uneven sizes swept together: one persistent
+ * launch per trip covers every tile of every problem (largest problems first,
+ * one ticket counter), and the schedule of each distinct n_steps is captured
+ * once into a hipGraph and replayed.  Both grids of problem q are dense boxes
+ * (nx+2)(ny+2)(nz+2) doubles, caller-owned; grid0[q] holds the initial box
+ * before jacobi_batch_create (which copies it into grid1[q]).
+ * With t == 0 the library's autotuner times its candidate (t, tile shape)
+ * configurations on the first sweeps of the batch (HIP events; FP64: these
+ * are real sweeps and count toward n_steps; FP32-refined: FP32 trips of the
+ * correction grids, the iterate is untouched) and keeps the fastest. */
+typedef struct {
+    int32_t count;            /* number of problems, >= 1 */
+    int32_t dtype;            /* JACOBI_F64 or JACOBI_F32_REFINED */
+    const int64_t *dims;      /* host array [count][3]: nx, ny, nz */
+    void *const *grid0;       /* host array [count] of device pointers */
+    void *const *grid1;       /* host array [count] of device pointers */
+    int32_t t;                /* sweeps per trip 1..8; 0 = autotune */
+    int32_t tile_rows;        /* with t > 0: tile shape (0 = default) */
+    int32_t rows_per_wave;
+    int32_t inner_sweeps;     /* JACOBI_F32_REFINED: FP32 sweeps per outer step */
+    int32_t use_graph;        /* nonzero: capture/replay hipGraphs */
+    int32_t reserved;
+    void *workspace;          /* device, 256-byte aligned */
+    size_t workspace_bytes;
+    void *stream;
+} jacobi_batch_desc;
+
+typedef struct jacobi_batch_s jacobi_batch_t;
+
+int jacobi_batch_workspace_size(const jacobi_batch_desc *d, size_t *bytes);
+int jacobi_batch_create(const jacobi_batch_desc *d, jacobi_batch_t **out);
+/* n_steps sweeps of every problem (F32_REFINED: FP32 inner sweeps grouped in
+ * outer steps of inner_sweeps).  Asynchronous apart from the first call of
+ * an autotuned batch (which synchronizes to read its timers). */
+int jacobi_batch_sweep(jacobi_batch_t *h, int64_t n_steps);
+/* Per-problem residual norms (and optional max |r|), host arrays [count];
+ * synchronizes. */
+int jacobi_batch_residual(jacobi_batch_t *h, double *l2, double *maxabs);
+int jacobi_batch_current(jacobi_batch_t *h, int32_t i, void **origin,
+                         int64_t strides[3]);
+/* Sweeps done, chosen configuration, and the time spent tuning (ms). */
+int jacobi_batch_info(jacobi_batch_t *h, int64_t *sweeps_done, int32_t *t,
+                      int32_t *tile_rows, int32_t *rows_per_wave,
+                      double *tune_ms);
+/* The autotuner's measurements: up to `cap` entries; *n = entries made. */
+int jacobi_batch_tune_log(jacobi_batch_t *h, int32_t cap, int32_t *t,
+                          int32_t *tile_rows, int32_t *rows_per_wave,
+                          double *glups, int32_t *n);
+int jacobi_batch_sync(jacobi_batch_t *h);
+int jacobi_batch_destroy(jacobi_batch_t *h);
+
 /* ---- bandwidth probes (Table 1 of the paper: STREAM copy and the
  *      array-update loop a[i] += 1 of Sect. 2.3) ---------------------------
  * n doubles, n even, 16-byte aligned device buffers; asynchronous. */

@@ -57,11 +57,26 @@ class JacobiDesc(ctypes.Structure):
     ]
 
 
+class JacobiBatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("dims", ctypes.POINTER(ctypes.c_int64)),
+        ("grid0", ctypes.POINTER(ctypes.c_void_p)),
+        ("grid1", ctypes.POINTER(ctypes.c_void_p)),
+        ("t", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+        ("rows_per_wave", ctypes.c_int32), ("inner_sweeps", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
 _h = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _descp = ctypes.POINTER(JacobiDesc)
+_bdescp = ctypes.POINTER(JacobiBatchDesc)
 
 _SIGS = {
     "jacobi_grid_bytes": ([_descp, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -77,6 +92,18 @@ _SIGS = {
     "jacobi_destroy": ([_h], ctypes.c_int),
     "jacobi_last_error": ([], ctypes.c_char_p),
     "jacobi_tile_supported": ([ctypes.c_int32] * 4, ctypes.c_int),
+    "jacobi_batch_workspace_size": ([_bdescp, ctypes.POINTER(ctypes.c_size_t)],
+                                    ctypes.c_int),
+    "jacobi_batch_create": ([_bdescp, ctypes.POINTER(_h)], ctypes.c_int),
+    "jacobi_batch_sweep": ([_h, ctypes.c_int64], ctypes.c_int),
+    "jacobi_batch_residual": ([_h, _dp, _dp], ctypes.c_int),
+    "jacobi_batch_current": ([_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                              _i64p], ctypes.c_int),
+    "jacobi_batch_info": ([_h, _i64p, _i32p, _i32p, _i32p, _dp], ctypes.c_int),
+    "jacobi_batch_tune_log": ([_h, ctypes.c_int32, _i32p, _i32p, _i32p, _dp, _i32p],
+                              ctypes.c_int),
+    "jacobi_batch_sync": ([_h], ctypes.c_int),
+    "jacobi_batch_destroy": ([_h], ctypes.c_int),
     "jacobi_probe_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                            ctypes.c_void_p], ctypes.c_int),
     "jacobi_probe_update": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],

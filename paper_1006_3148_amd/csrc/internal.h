@@ -8,6 +8,18 @@
 
 namespace jacobi_impl {
 
+// One problem of a batch (device-resident table, MODE 2 of the trip kernel).
+// grid[0], grid[1]: logical (0,0,0) of the two A/B frames; tile_base: number
+// of tiles of all earlier problems in the table.
+struct BatchProblem {
+    void* grid[2];
+    const float* rhs;
+    int64_t px, py;
+    int nx, ny, nz;
+    int tiles_x, tiles_y, segs, seg_len;
+    int tile_base;
+};
+
 // Geometry and pointers of one trip launch (t fused sweeps, one pass through
 // HBM).  All pointers address logical cell (0,0,0) of their frame; cell
 // (i,j,k) of a frame lives at origin + k*py + j*px + i.
@@ -21,12 +33,17 @@ struct TripParams {
     int nx, ny, nz;    // interior dims
     int tiles_x, tiles_y, segs, seg_len;
     int ntiles;
-    int mode;          // 0: blockIdx tiles (A/B); 1: tickets + flags (compressed)
+    int mode;          // 0: blockIdx tiles (A/B); 1: tickets + flags
+                       // (compressed); 2: batch table, tickets
     int dir;           // +1 forward shift (-t), -1 backward shift (+t); mode 1
     int* flags;        // per-tile progress words, stride kFlagStride ints
     int* ticket;       // ticket counter (zeroed before the launch)
     int* err;          // error word: 0 ok, nonzero = watchdog fired
     int64_t spin_limit;
+    const BatchProblem* table;  // mode 2: problems (device memory)
+    int count;                  // mode 2: number of problems
+    const int* parity;          // mode 2: A/B parity word (device memory)
+    int rhs_in_table;           // mode 2: FP32 rhs pointers are in the table
 };
 
 constexpr int kFlagStride = 32;  // ints per flag (128 B line each)
@@ -48,26 +65,52 @@ bool trip_config_supported(int dtype_f32, const TripConfig& cfg);
 hipError_t launch_fill_i32(int* p, int value, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float value, int64_t n, hipStream_t s);
 
-// Residual r = fold(nbrs) - 6u on the interior.  Pass 1 writes per-block
-// partial sums of r^2 (and max |r|) into `partials` (2*nblocks doubles);
-// pass 2 reduces them in fixed order into out[0] = ||r||_2, out[1] = max|r|.
-int residual_blocks(int nx, int ny, int nz);
-hipError_t launch_residual(const double* u, int64_t px, int64_t py, int nx,
-                           int ny, int nz, double* partials, double* out,
-                           hipStream_t s);
+// One problem for the residual / refinement kernels.  u[par]: logical
+// (0,0,0) of the FP64 iterate (par = *parity when a parity word is given,
+// else 0); e[0..1], rhs: dense FP32 boxes of the refinement (may be null).
+struct AuxProblem {
+    const double* u[2];
+    float* e[2];
+    float* rhs;
+    int64_t px, py;     // pitches of u
+    int64_t epx, epy;   // pitches of e / rhs
+    int nx, ny, nz;
+    int rtx, rty, rsegs, rseg_len;  // residual tiling (64 x 4 columns x seg)
+    int rblocks, rblock_base;       // residual blocks of this problem, prefix
+};
 
-// FP32 refinement helpers.
-//  rhs = fl32(r * 2^-s) with s = frexp exponent of out[1] (max|r|) read on the
-//  device; the exponent is stored in *scale_exp.
-hipError_t launch_make_rhs(const double* u, int64_t px, int64_t py, int nx,
-                           int ny, int nz, const double* maxabs,
-                           int* scale_exp, float* rhs, int64_t rpx,
-                           int64_t rpy, hipStream_t s);
-//  u(interior) += fl64(e) * 2^scale_exp
-hipError_t launch_apply_correction(double* u, int64_t px, int64_t py, int nx,
-                                   int ny, int nz, const float* e,
-                                   int64_t epx, int64_t epy,
-                                   const int* scale_exp, hipStream_t s);
+// Fills the residual tiling fields of `a` (rtx..rblocks); returns rblocks.
+int residual_plan(AuxProblem* a);
+
+// Residual r = fold(nbrs) - 6u on the interior of each problem.
+// Pass 1 (k-streaming, one block per 64x4-column tile and k segment) writes
+// (sum r^2, max|r|) per block into partials[2*b], partials[2*b+1]; pass 2
+// reduces each problem's blocks in fixed order into out[2*q] = ||r||_2,
+// out[2*q+1] = max|r|.  `table` (device) with `count` problems, or `table`
+// null and the single problem `one` passed by value.  `total_blocks` = sum of
+// rblocks.
+hipError_t launch_residual_tab(const AuxProblem* table, int count,
+                               const AuxProblem& one, const int* parity,
+                               int total_blocks, double* partials, double* out,
+                               hipStream_t s);
+
+// FP32 refinement helpers, per problem q: rhs_q = fl32(r_q * 2^-s_q) with s_q
+// the frexp exponent of out[2q+1] (max |r|), written to scale_exp[q].
+hipError_t launch_make_rhs_tab(const AuxProblem* table, int count,
+                               const AuxProblem& one, const int* parity,
+                               const double* out, int* scale_exp,
+                               hipStream_t s);
+// u_q(interior) += fl64(e_q[which]) * 2^scale_exp[q]
+hipError_t launch_apply_correction_tab(const AuxProblem* table, int count,
+                                       const AuxProblem& one,
+                                       const int* parity, int which,
+                                       const int* scale_exp, hipStream_t s);
+// e_q[0] = 0 (whole box) for every problem.
+hipError_t launch_zero_e_tab(const AuxProblem* table, int count,
+                             const AuxProblem& one, hipStream_t s);
+// *word ^= 1 (A/B parity flip between batched trips) and ticket = 0.
+hipError_t launch_flip_parity(int* word, int* ticket, hipStream_t s);
+hipError_t launch_set_int(int* word, int value, hipStream_t s);
 
 // Box copy between frames of the same logical dims (used to seed the second
 // grid and for compressed-layout moves).

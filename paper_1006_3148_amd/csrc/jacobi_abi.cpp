@@ -18,12 +18,17 @@
 
 #include "jacobi.h"
 #include "internal.h"
+#include "runtime_common.h"
 
 using namespace jacobi_impl;
 
-namespace {
+namespace jacobi_impl {
 
+namespace {
 thread_local std::string g_err;
+}
+
+const char* last_error_text() { return g_err.c_str(); }
 
 int fail(int code, const char* fmt, ...)
 {
@@ -41,15 +46,6 @@ int hip_fail(hipError_t e, const char* what)
     return fail(JACOBI_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-constexpr int kCUs = 256;  // MI355X compute units
-
-struct Plan {
-    TripConfig cfg;
-    int tiles_x = 0, tiles_y = 0, segs = 0, seg_len = 0, ntiles = 0;
-};
-
-// Default tile shape per sweeps-per-trip (chosen so the per-stage register
-// state fits without spilling; see the trip kernel).
 TripConfig default_cfg(int T)
 {
     if (T <= 2) return TripConfig{T, 4, 16};
@@ -57,10 +53,8 @@ TripConfig default_cfg(int T)
     return TripConfig{T, 2, 16};
 }
 
-int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
-
 bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
-               int seg_req, bool compressed, Plan* out)
+               int seg_req, bool compressed, int target_tiles, Plan* out)
 {
     const int T = cfg.T;
     const int OX = 64 - 2 * T;
@@ -78,6 +72,7 @@ bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
         p.seg_len = (int)std::min<int64_t>(seg_req, nz2);
     } else {
         // Minimise (rounds of concurrent tiles) x (planes each tile streams).
+        const int conc = target_tiles > 0 ? target_tiles : kCUs;
         double best = 1e300;
         int best_len = (int)nz2;
         const int min_len = std::max(compressed ? 2 * T : 1, 4 * T);
@@ -86,7 +81,7 @@ bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
             if (len < min_len && segs > 1) break;
             const int64_t real_segs = (nz2 + len - 1) / len;
             const int64_t tiles = plane_tiles * real_segs;
-            const int64_t rounds = (tiles + kCUs - 1) / kCUs;
+            const int64_t rounds = (tiles + conc - 1) / conc;
             const double cost = (double)rounds * (double)(len + 1.5 * T);
             if (cost < best * 0.999) {
                 best = cost;
@@ -103,7 +98,7 @@ bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
     return true;
 }
 
-}  // namespace
+}  // namespace jacobi_impl
 
 struct jacobi_s {
     jacobi_desc d{};
@@ -129,6 +124,7 @@ struct jacobi_s {
     int64_t flag_ints = 0;
     float* e[2] = {nullptr, nullptr};
     float* rhs = nullptr;
+    AuxProblem aux{};         // residual / refinement view of this problem
 };
 
 namespace {
@@ -177,7 +173,7 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                         "tile shape t=%d rows=%d rows_per_wave=%d is not compiled",
                         T, cfg.R * cfg.W, cfg.R);
         if (!make_plan(d->nx, d->ny, d->nz, cfg, T == t ? d->seg_len : 0, comp,
-                       &plans[T]))
+                       kCUs, &plans[T]))
             return fail(JACOBI_EUNSUPPORTED,
                         "tile shape t=%d rows=%d cannot cover this box%s", T,
                         cfg.R * cfg.W,
@@ -186,9 +182,13 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     }
     *t_out = t;
     Layout L{};
-    const int nb = residual_blocks((int)d->nx, (int)d->ny, (int)d->nz);
+    AuxProblem ap{};
+    ap.nx = (int)d->nx;
+    ap.ny = (int)d->ny;
+    ap.nz = (int)d->nz;
+    const int nb = residual_plan(&ap);
     L.partials_off = 256;
-    L.flags_off = (size_t)round_up(L.partials_off + 2 * nb * sizeof(double), 256);
+    L.flags_off = (size_t)round_up(L.partials_off + 2 * (int64_t)nb * sizeof(double), 256);
     L.flag_ints = comp ? max_tiles * kFlagStride : 0;
     size_t end = (size_t)round_up(L.flags_off + L.flag_ints * sizeof(int), 256);
     L.e0_off = L.e1_off = L.rhs_off = 0;
@@ -290,19 +290,27 @@ int run_f64(jacobi_t* h, int64_t n)
     return JACOBI_OK;
 }
 
+// Residual / refinement view of the current iterate.
+const AuxProblem& aux_view(jacobi_t* h)
+{
+    h->aux.u[0] = current_origin(h);
+    h->aux.u[1] = h->aux.u[0];
+    return h->aux;
+}
+
 // One outer step of the FP32-refined iteration with m inner sweeps.
 int outer_f32(jacobi_t* h, int64_t m)
 {
     const int nx = (int)h->d.nx, ny = (int)h->d.ny, nz = (int)h->d.nz;
     const int64_t epx = nx + 2, epy = (int64_t)(nx + 2) * (ny + 2);
-    double* u = current_origin(h);
-    hipError_t e = launch_residual(u, h->px, h->py, nx, ny, nz, h->partials,
-                                   h->red_out, h->stream);
+    (void)nz;
+    const AuxProblem& a = aux_view(h);
+    hipError_t e = launch_residual_tab(nullptr, 1, a, nullptr, a.rblocks,
+                                       h->partials, h->red_out, h->stream);
     if (e == hipSuccess)
-        e = launch_make_rhs(u, h->px, h->py, nx, ny, nz, h->red_out + 1,
-                            h->scale_exp, h->rhs, epx, epy, h->stream);
-    if (e == hipSuccess)
-        e = launch_fill_f32(h->e[0], 0.f, epy * (nz + 2), h->stream);
+        e = launch_make_rhs_tab(nullptr, 1, a, nullptr, h->red_out, h->scale_exp,
+                                h->stream);
+    if (e == hipSuccess) e = launch_zero_e_tab(nullptr, 1, a, h->stream);
     if (e != hipSuccess) return hip_fail(e, "refinement set-up");
     int ce = 0;
     int64_t left = m;
@@ -313,8 +321,8 @@ int outer_f32(jacobi_t* h, int64_t m)
         ce ^= 1;
         left -= L;
     }
-    e = launch_apply_correction(u, h->px, h->py, nx, ny, nz, h->e[ce], epx, epy,
-                                h->scale_exp, h->stream);
+    e = launch_apply_correction_tab(nullptr, 1, a, nullptr, ce, h->scale_exp,
+                                    h->stream);
     if (e != hipSuccess) return hip_fail(e, "correction launch");
     h->sweeps += m;
     return JACOBI_OK;
@@ -341,7 +349,7 @@ int check_pending(jacobi_t* h)
 
 extern "C" {
 
-const char* jacobi_last_error(void) { return g_err.c_str(); }
+const char* jacobi_last_error(void) { return last_error_text(); }
 
 int jacobi_tile_supported(int32_t dtype, int32_t t, int32_t tile_rows,
                           int32_t rows_per_wave)
@@ -429,6 +437,18 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
         h->e[1] = reinterpret_cast<float*>(h->ws + L.e1_off);
         h->rhs = reinterpret_cast<float*>(h->ws + L.rhs_off);
     }
+    h->aux.nx = (int)d->nx;
+    h->aux.ny = (int)d->ny;
+    h->aux.nz = (int)d->nz;
+    h->aux.px = h->px;
+    h->aux.py = h->py;
+    h->aux.epx = d->nx + 2;
+    h->aux.epy = (d->nx + 2) * (d->ny + 2);
+    h->aux.e[0] = h->e[0];
+    h->aux.e[1] = h->e[1];
+    h->aux.rhs = h->rhs;
+    residual_plan(&h->aux);
+    h->aux.rblock_base = 0;
     hipError_t e = launch_fill_i32(h->ticket, 0, 16, h->stream);
     if (e == hipSuccess && d->layout == JACOBI_LAYOUT_AB) {
         const int nx2 = (int)d->nx + 2, ny2 = (int)d->ny + 2, nz2 = (int)d->nz + 2;
@@ -467,9 +487,9 @@ int jacobi_sweep(jacobi_t* h, int64_t n_steps)
 int jacobi_residual(jacobi_t* h, double* l2, double* maxabs)
 {
     if (!h || !l2) return fail(JACOBI_EINVAL, "null argument");
-    hipError_t e = launch_residual(current_origin(h), h->px, h->py, (int)h->d.nx,
-                                   (int)h->d.ny, (int)h->d.nz, h->partials,
-                                   h->red_out, h->stream);
+    const AuxProblem& a = aux_view(h);
+    hipError_t e = launch_residual_tab(nullptr, 1, a, nullptr, a.rblocks,
+                                       h->partials, h->red_out, h->stream);
     if (e != hipSuccess) return hip_fail(e, "residual launch");
     double out[2] = {0, 0};
     e = hipMemcpyAsync(out, h->red_out, sizeof out, hipMemcpyDeviceToHost, h->stream);

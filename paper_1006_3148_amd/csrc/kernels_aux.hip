@@ -15,19 +15,7 @@ namespace {
 
 constexpr int kRedThreads = 256;
 constexpr int kNoCorrection = -2147483647 - 1;
-constexpr int kMaxRedBlocks = 2048;
-
-__device__ __forceinline__ double resid_at(const double* __restrict__ u,
-                                           int64_t c, int64_t px, int64_t py)
-{
-    double s = u[c - 1];
-    s = s + u[c + 1];
-    s = s + u[c - px];
-    s = s + u[c + px];
-    s = s + u[c - py];
-    s = s + u[c + py];
-    return s - 6.0 * u[c];
-}
+constexpr int kRX = 64, kRY = 4;  // residual block: 64 i-lanes x 4 j-rows
 
 // Block tree reduction of (sum, max) in a fixed order.
 __device__ __forceinline__ void block_reduce(double& sum, double& mx,
@@ -48,90 +36,192 @@ __device__ __forceinline__ void block_reduce(double& sum, double& mx,
     mx = sh_max[0];
 }
 
-// Pass 1: block b owns the interior rows (j,k) with row index = b mod
-// gridDim.x; each thread owns i = 1 + t, 1 + t + 256, ...
+// Problem owning global residual block b (binary search over rblock_base).
+__device__ __forceinline__ const AuxProblem* find_rblock(const AuxProblem* tab,
+                                                        int count, int b)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].rblock_base <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return tab + lo;
+}
+
+__device__ __forceinline__ double resid_at(const double* __restrict__ c,
+                                           int64_t px, double um, double up,
+                                           double uc)
+{
+    double s = c[-1];
+    s = s + c[1];
+    s = s + c[-px];
+    s = s + c[px];
+    s = s + um;
+    s = s + up;
+    return s - 6.0 * uc;
+}
+
+// Pass 1: k-streaming residual.  Each thread owns one interior column (i, j)
+// of a 64 x 4 tile and one k segment; the k-1 / k / k+1 values stay in
+// registers, the in-plane neighbours come through L1/L2.
 __global__ __launch_bounds__(kRedThreads) void residual_pass1(
-    const double* __restrict__ u, int64_t px, int64_t py, int nx, int ny,
-    int nz, double* __restrict__ partials)
+    const AuxProblem* __restrict__ tab, int count, AuxProblem one,
+    const int* __restrict__ parity, double* __restrict__ partials)
 {
     __shared__ double sh_sum[kRedThreads], sh_max[kRedThreads];
+    const AuxProblem Pv = tab ? *find_rblock(tab, count, blockIdx.x) : one;
+    const AuxProblem* P = &Pv;
+    const int lb = blockIdx.x - P->rblock_base;
+    const int tx = lb % P->rtx;
+    const int rest = lb / P->rtx;
+    const int ty = rest % P->rty;
+    const int sg = rest / P->rty;
+    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+    const int i = 1 + tx * kRX + lane;
+    const int j = 1 + ty * kRY + row;
+    const int k0 = 1 + sg * P->rseg_len;
+    const int k1 = min(k0 + P->rseg_len, P->nz + 1);
+    const int64_t px = P->px, py = P->py;
+    const double* __restrict__ u = ((parity && (*parity & 1)) ? P->u[1] : P->u[0]);
     double sum = 0.0, mx = 0.0;
-    const int64_t rows = (int64_t)ny * nz;
-    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int j = 1 + (int)(row % ny);
-        const int k = 1 + (int)(row / ny);
-        const int64_t base = (int64_t)k * py + (int64_t)j * px;
-        for (int i = 1 + threadIdx.x; i <= nx; i += kRedThreads) {
-            const double r = resid_at(u, base + i, px, py);
+    if (i <= P->nx && j <= P->ny) {
+        const double* col = u + (int64_t)j * px + i;
+        double um = col[(int64_t)(k0 - 1) * py];
+        double uc = col[(int64_t)k0 * py];
+        double up = col[(int64_t)(k0 + 1) * py];
+        for (int k = k0; k < k1; ++k) {
+            const double upp = (k + 2 <= P->nz + 1) ? col[(int64_t)(k + 2) * py] : 0.0;
+            const double r = resid_at(col + (int64_t)k * py, px, um, up, uc);
             sum = sum + r * r;
             mx = fmax(mx, fabs(r));
+            um = uc;
+            uc = up;
+            up = upp;
         }
     }
     block_reduce(sum, mx, sh_sum, sh_max);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = sum;
-        partials[gridDim.x + blockIdx.x] = mx;
+        partials[2 * (int64_t)blockIdx.x] = sum;
+        partials[2 * (int64_t)blockIdx.x + 1] = mx;
     }
 }
 
+// Pass 2: block q reduces problem q's partials in a fixed order.
 __global__ __launch_bounds__(kRedThreads) void residual_pass2(
-    const double* __restrict__ partials, int nblocks, double* __restrict__ out)
+    const AuxProblem* __restrict__ tab, AuxProblem one,
+    const double* __restrict__ partials, double* __restrict__ out)
 {
     __shared__ double sh_sum[kRedThreads], sh_max[kRedThreads];
+    const AuxProblem Pv = tab ? tab[blockIdx.x] : one;
+    const AuxProblem* P = &Pv;
     double sum = 0.0, mx = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
-        sum = sum + partials[b];
-        mx = fmax(mx, partials[nblocks + b]);
+    for (int b = threadIdx.x; b < P->rblocks; b += kRedThreads) {
+        const int64_t g = P->rblock_base + b;
+        sum = sum + partials[2 * g];
+        mx = fmax(mx, partials[2 * g + 1]);
     }
     block_reduce(sum, mx, sh_sum, sh_max);
     if (threadIdx.x == 0) {
-        out[0] = sqrt(sum);
-        out[1] = mx;
+        out[2 * blockIdx.x] = sqrt(sum);
+        out[2 * blockIdx.x + 1] = mx;
     }
 }
 
-// rhs = fl32(r * 2^-s), s = frexp exponent of max|r|.
-__global__ __launch_bounds__(256) void make_rhs_kernel(
-    const double* __restrict__ u, int64_t px, int64_t py, int nx, int ny,
-    int nz, const double* __restrict__ maxabs, int* __restrict__ scale_exp,
-    float* __restrict__ rhs, int64_t rpx, int64_t rpy)
+__device__ __forceinline__ double resid_plain(const double* __restrict__ u,
+                                              int64_t c, int64_t px, int64_t py)
 {
-    const double m = *maxabs;
+    double s = u[c - 1];
+    s = s + u[c + 1];
+    s = s + u[c - px];
+    s = s + u[c + px];
+    s = s + u[c - py];
+    s = s + u[c + py];
+    return s - 6.0 * u[c];
+}
+
+// rhs = fl32(r * 2^-s), s = frexp exponent of max|r|; blockIdx.y = problem.
+__global__ __launch_bounds__(256) void make_rhs_kernel(
+    const AuxProblem* __restrict__ tab, AuxProblem one,
+    const int* __restrict__ parity, const double* __restrict__ out,
+    int* __restrict__ scale_exp)
+{
+    const int q = blockIdx.y;
+    const AuxProblem Pv = tab ? tab[q] : one;
+    const AuxProblem* P = &Pv;
+    const double m = out[2 * q + 1];
     int s = 0;
     if (m > 0.0) frexp(m, &s);
     // kNoCorrection tells the update kernel that the field is already exact.
-    if (blockIdx.x == 0 && threadIdx.x == 0) *scale_exp = m > 0.0 ? s : kNoCorrection;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        scale_exp[q] = m > 0.0 ? s : kNoCorrection;
+    const double* __restrict__ u = ((parity && (*parity & 1)) ? P->u[1] : P->u[0]);
+    float* __restrict__ rhs = P->rhs;
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
     const int64_t rows = (int64_t)ny * nz;
     for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
         const int j = 1 + (int)(row % ny);
         const int k = 1 + (int)(row / ny);
-        const int64_t base = (int64_t)k * py + (int64_t)j * px;
-        const int64_t rbase = (int64_t)k * rpy + (int64_t)j * rpx;
+        const int64_t base = (int64_t)k * P->py + (int64_t)j * P->px;
+        const int64_t rbase = (int64_t)k * P->epy + (int64_t)j * P->epx;
         for (int i = 1 + threadIdx.x; i <= nx; i += blockDim.x) {
             float v = 0.f;
-            if (m > 0.0) v = (float)ldexp(resid_at(u, base + i, px, py), -s);
+            if (m > 0.0) v = (float)ldexp(resid_plain(u, base + i, P->px, P->py), -s);
             rhs[rbase + i] = v;
         }
     }
 }
 
 __global__ __launch_bounds__(256) void apply_correction_kernel(
-    double* __restrict__ u, int64_t px, int64_t py, int nx, int ny, int nz,
-    const float* __restrict__ e, int64_t epx, int64_t epy,
+    const AuxProblem* __restrict__ tab, AuxProblem one,
+    const int* __restrict__ parity, int which,
     const int* __restrict__ scale_exp)
 {
-    const int s = *scale_exp;
+    const int q = blockIdx.y;
+    const AuxProblem Pv = tab ? tab[q] : one;
+    const AuxProblem* P = &Pv;
+    const int s = scale_exp[q];
     if (s == kNoCorrection) return;
+    double* __restrict__ u = const_cast<double*>(((parity && (*parity & 1)) ? P->u[1] : P->u[0]));
+    const float* __restrict__ e = which ? P->e[1] : P->e[0];
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
     const int64_t rows = (int64_t)ny * nz;
     for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
         const int j = 1 + (int)(row % ny);
         const int k = 1 + (int)(row / ny);
-        const int64_t base = (int64_t)k * py + (int64_t)j * px;
-        const int64_t ebase = (int64_t)k * epy + (int64_t)j * epx;
-        for (int i = 1 + threadIdx.x; i <= nx; i += blockDim.x) {
+        const int64_t base = (int64_t)k * P->py + (int64_t)j * P->px;
+        const int64_t ebase = (int64_t)k * P->epy + (int64_t)j * P->epx;
+        for (int i = 1 + threadIdx.x; i <= nx; i += blockDim.x)
             u[base + i] = u[base + i] + ldexp((double)e[ebase + i], s);
-        }
     }
+}
+
+__global__ __launch_bounds__(256) void zero_e_kernel(
+    const AuxProblem* __restrict__ tab, AuxProblem one)
+{
+    const AuxProblem Pv = tab ? tab[blockIdx.y] : one;
+    float* __restrict__ e = Pv.e[0];
+    const AuxProblem* P = &Pv;
+    const int64_t n = P->epy * (P->nz + 2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += stride)
+        e[x] = 0.f;
+}
+
+__global__ void flip_parity_kernel(int* word, int* ticket)
+{
+    if (threadIdx.x == 0) {
+        *word = *word ^ 1;
+        *ticket = 0;
+    }
+}
+
+__global__ void set_int_kernel(int* word, int value)
+{
+    if (threadIdx.x == 0) *word = value;
 }
 
 template <typename V>
@@ -201,11 +291,6 @@ __global__ __launch_bounds__(256) void stream_update_kernel(
     }
 }
 
-int grid_for_rows(int64_t rows)
-{
-    return (int)(rows < 65536 ? rows : 65536);
-}
-
 int grid_for_elems(int64_t n)
 {
     int64_t g = (n + 255) / 256;
@@ -216,44 +301,83 @@ int grid_for_elems(int64_t n)
 
 }  // namespace
 
-int residual_blocks(int nx, int ny, int nz)
+int residual_plan(AuxProblem* a)
 {
-    (void)nx;
-    const int64_t rows = (int64_t)ny * nz;
-    return (int)(rows < kMaxRedBlocks ? rows : kMaxRedBlocks);
+    a->rtx = (a->nx + kRX - 1) / kRX;
+    a->rty = (a->ny + kRY - 1) / kRY;
+    const int64_t plane = (int64_t)a->rtx * a->rty;
+    // Enough blocks to fill the chip (>= 2048) with segments of >= 16 planes.
+    int64_t segs = (2048 + plane - 1) / plane;
+    const int64_t max_segs = (a->nz + 15) / 16;
+    if (segs > max_segs) segs = max_segs;
+    if (segs < 1) segs = 1;
+    a->rseg_len = (int)((a->nz + segs - 1) / segs);
+    a->rsegs = (a->nz + a->rseg_len - 1) / a->rseg_len;
+    a->rblocks = (int)(plane * a->rsegs);
+    return a->rblocks;
 }
 
-hipError_t launch_residual(const double* u, int64_t px, int64_t py, int nx,
-                           int ny, int nz, double* partials, double* out,
-                           hipStream_t s)
+namespace {
+int grid_rows(int64_t rows, int count)
 {
-    const int nb = residual_blocks(nx, ny, nz);
-    hipLaunchKernelGGL(residual_pass1, dim3(nb), dim3(kRedThreads), 0, s, u, px,
-                       py, nx, ny, nz, partials);
-    hipLaunchKernelGGL(residual_pass2, dim3(1), dim3(kRedThreads), 0, s,
-                       partials, nb, out);
+    int64_t g = rows < 4096 ? rows : 4096;
+    if (count > 1 && g > 512) g = 512;
+    return (int)(g < 1 ? 1 : g);
+}
+}  // namespace
+
+hipError_t launch_residual_tab(const AuxProblem* table, int count,
+                               const AuxProblem& one, const int* parity,
+                               int total_blocks, double* partials, double* out,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(residual_pass1, dim3(total_blocks), dim3(kRedThreads), 0,
+                       s, table, count, one, parity, partials);
+    hipLaunchKernelGGL(residual_pass2, dim3(table ? count : 1), dim3(kRedThreads),
+                       0, s, table, one, partials, out);
     return hipGetLastError();
 }
 
-hipError_t launch_make_rhs(const double* u, int64_t px, int64_t py, int nx,
-                           int ny, int nz, const double* maxabs,
-                           int* scale_exp, float* rhs, int64_t rpx,
-                           int64_t rpy, hipStream_t s)
+hipError_t launch_make_rhs_tab(const AuxProblem* table, int count,
+                               const AuxProblem& one, const int* parity,
+                               const double* out, int* scale_exp, hipStream_t s)
 {
-    hipLaunchKernelGGL(make_rhs_kernel, dim3(grid_for_rows((int64_t)ny * nz)),
-                       dim3(256), 0, s, u, px, py, nx, ny, nz, maxabs,
-                       scale_exp, rhs, rpx, rpy);
+    const int64_t rows = table ? (int64_t)512 : (int64_t)one.ny * one.nz;
+    hipLaunchKernelGGL(make_rhs_kernel,
+                       dim3(grid_rows(rows, table ? count : 1), table ? count : 1),
+                       dim3(256), 0, s, table, one, parity, out, scale_exp);
     return hipGetLastError();
 }
 
-hipError_t launch_apply_correction(double* u, int64_t px, int64_t py, int nx,
-                                   int ny, int nz, const float* e,
-                                   int64_t epx, int64_t epy,
-                                   const int* scale_exp, hipStream_t s)
+hipError_t launch_apply_correction_tab(const AuxProblem* table, int count,
+                                       const AuxProblem& one,
+                                       const int* parity, int which,
+                                       const int* scale_exp, hipStream_t s)
 {
+    const int64_t rows = table ? (int64_t)512 : (int64_t)one.ny * one.nz;
     hipLaunchKernelGGL(apply_correction_kernel,
-                       dim3(grid_for_rows((int64_t)ny * nz)), dim3(256), 0, s,
-                       u, px, py, nx, ny, nz, e, epx, epy, scale_exp);
+                       dim3(grid_rows(rows, table ? count : 1), table ? count : 1),
+                       dim3(256), 0, s, table, one, parity, which, scale_exp);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_e_tab(const AuxProblem* table, int count,
+                             const AuxProblem& one, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_e_kernel, dim3(table ? 256 : 2048, table ? count : 1),
+                       dim3(256), 0, s, table, one);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_parity(int* word, int* ticket, hipStream_t s)
+{
+    hipLaunchKernelGGL(flip_parity_kernel, dim3(1), dim3(64), 0, s, word, ticket);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* word, int value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(64), 0, s, word, value);
     return hipGetLastError();
 }
 
@@ -278,7 +402,7 @@ hipError_t launch_copy_box_f64(const double* src, int64_t spx, int64_t spy,
                                int ny2, int nz2, hipStream_t s)
 {
     hipLaunchKernelGGL(copy_box_kernel,
-                       dim3(grid_for_rows((int64_t)ny2 * nz2)), dim3(256), 0, s,
+                       dim3((int)((int64_t)ny2 * nz2 < 65536 ? (int64_t)ny2 * nz2 : 65536)), dim3(256), 0, s,
                        src, spx, spy, dst, dpx, dpy, nx2, ny2, nz2);
     return hipGetLastError();
 }

@@ -114,8 +114,18 @@ constexpr int kDone = 0x7fffffff;
 #endif
 constexpr int kPrefetch = JACOBI_PREFETCH;
 
+// Geometry and pointers of the problem a tile belongs to.
+struct Geo {
+    const void* src;
+    void* dst;
+    const float* rhs;
+    int64_t px, py, rpx, rpy;
+    int nx, ny, nz;
+    int tiles_x, tiles_y, segs, seg_len;
+};
+
 template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE>
-__device__ __forceinline__ void run_tile(const TripParams& p, int tile,
+__device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int tile,
                                          Real (*xch)[W][2][64])
 {
     constexpr int H = R * W;
@@ -126,22 +136,22 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-    const int tx = tile % p.tiles_x;
-    const int rest = tile / p.tiles_x;
-    const int ty = rest % p.tiles_y;
-    const int seg = rest / p.tiles_y;
+    const int tx = tile % g.tiles_x;
+    const int rest = tile / g.tiles_x;
+    const int ty = rest % g.tiles_y;
+    const int seg = rest / g.tiles_y;
 
     const int i = tx * OX - T + lane;
     const int j0 = ty * OY - T + wave * R;
-    const int k0 = seg * p.seg_len;
-    const int k1 = min(k0 + p.seg_len, p.nz + 2);
+    const int k0 = seg * g.seg_len;
+    const int k1 = min(k0 + g.seg_len, g.nz + 2);
     const int a = max(k0 - T, 0);
-    const int b = min(k1 - 1 + T, p.nz + 1);
+    const int b = min(k1 - 1 + T, g.nz + 1);
     const int nsteps = k1 - a + T;
 
-    const Real* __restrict__ src = static_cast<const Real*>(p.src);
-    Real* __restrict__ dst = static_cast<Real*>(p.dst);
-    const int64_t px = p.px, py = p.py;
+    const Real* __restrict__ src = static_cast<const Real*>(g.src);
+    Real* __restrict__ dst = static_cast<Real*>(g.dst);
+    const int64_t px = g.px, py = g.py;
 
     bool lane_int = true, lane_box = true;
     bool row_int[R], row_box[R];
@@ -151,21 +161,21 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
         row_box[r] = true;
     }
     if (EDGE) {
-        lane_box = (unsigned)i <= (unsigned)(p.nx + 1);
-        lane_int = i >= 1 && i <= p.nx;
+        lane_box = (unsigned)i <= (unsigned)(g.nx + 1);
+        lane_int = i >= 1 && i <= g.nx;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int j = j0 + r;
-            row_box[r] = (unsigned)j <= (unsigned)(p.ny + 1);
-            row_int[r] = j >= 1 && j <= p.ny;
+            row_box[r] = (unsigned)j <= (unsigned)(g.ny + 1);
+            row_int[r] = j >= 1 && j <= g.ny;
         }
     }
-    const bool lane_out = lane >= T && lane < 64 - T && i <= p.nx + 1;
+    const bool lane_out = lane >= T && lane < 64 - T && i <= g.nx + 1;
     bool row_out[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int tr = wave * R + r;
-        row_out[r] = tr >= T && tr < H - T && (j0 + r) <= p.ny + 1;
+        row_out[r] = tr >= T && tr < H - T && (j0 + r) <= g.ny + 1;
     }
 
     // Dependees of this tile under the compressed-grid shift: the tiles whose
@@ -177,9 +187,9 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
         const int ntx = tx + ((d & 1) ? sgn : 0);
         const int nty = ty + ((d & 2) ? sgn : 0);
         const int nsg = seg + ((d & 4) ? sgn : 0);
-        if (ntx >= 0 && ntx < p.tiles_x && nty >= 0 && nty < p.tiles_y &&
-            nsg >= 0 && nsg < p.segs)
-            dep = (nsg * p.tiles_y + nty) * p.tiles_x + ntx;
+        if (ntx >= 0 && ntx < g.tiles_x && nty >= 0 && nty < g.tiles_y &&
+            nsg >= 0 && nsg < g.segs)
+            dep = (nsg * g.tiles_y + nty) * g.tiles_x + ntx;
     }
     int known = FLAGS ? 0 : kDone;
 
@@ -205,9 +215,9 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
         voff[r] = (uint32_t)(((int64_t)(j0 + r) * px + i) * (int64_t)sizeof(Real));
     const int64_t plane_bytes = py * (int64_t)sizeof(Real);
     const char* src_b = reinterpret_cast<const char*>(src);
-    const char* rhs_b = reinterpret_cast<const char*>(p.rhs);
+    const char* rhs_b = reinterpret_cast<const char*>(g.rhs);
     char* dst_b = reinterpret_cast<char*>(dst);
-    const int64_t rplane_bytes = p.rpy * (int64_t)sizeof(float);
+    const int64_t rplane_bytes = g.rpy * (int64_t)sizeof(float);
 
     // Register ring of the next PF input planes (and rhs planes): plane
     // loads are issued PF steps before use, so each step does not wait for a
@@ -230,7 +240,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 rring[RHS ? d : 0][r] = 0.f;
-                if (qr >= 1 && qr <= p.nz && (!EDGE || (lane_box && row_box[r])))
+                if (qr >= 1 && qr <= g.nz && (!EDGE || (lane_box && row_box[r])))
                     rring[RHS ? d : 0][r] = *reinterpret_cast<const float*>(
                         rp + voff[r] / (sizeof(Real) / sizeof(float)));
             }
@@ -269,7 +279,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
             const int qr = a + n + PF - 1;  // rhs plane stage 1 uses at step n+PF
 #pragma unroll
             for (int r = 0; r < R; ++r) rring[RHS ? PF - 1 : 0][r] = 0.f;
-            if (qr >= 1 && qr <= p.nz) {
+            if (qr >= 1 && qr <= g.nz) {
                 const char* rp = rhs_b + (int64_t)qr * rplane_bytes;
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -299,7 +309,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
                 }
                 const Real up = buf[wave > 0 ? wave - 1 : 0][1][lane];
                 const Real dn = buf[wave < W - 1 ? wave + 1 : W - 1][0][lane];
-                const bool bnd = BND && ((pe == 0) || (pe == p.nz + 1));
+                const bool bnd = BND && ((pe == 0) || (pe == g.nz + 1));
                 // Row by row; `above` keeps the old value of row r-1.
                 Real above = up;
 #pragma unroll
@@ -323,7 +333,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
                 }
             }
         };
-        if (a + n - T <= 0 || a + n - 1 >= p.nz + 1)
+        if (a + n - T <= 0 || a + n - 1 >= g.nz + 1)
             stages(std::true_type{});
         else
             stages(std::false_type{});
@@ -342,7 +352,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
                 // terms; planes outside the box are shift room nobody reads.
                 const int ow = p.dir > 0 ? pe - T : pe + T;
                 const int need = ow + 1;
-                if (ow >= 0 && ow <= p.nz + 1 && known < need) {
+                if (ow >= 0 && ow <= g.nz + 1 && known < need) {
                     int64_t spins = 0;
                     for (;;) {
                         int v = kDone;
@@ -379,9 +389,16 @@ __device__ __forceinline__ void run_tile(const TripParams& p, int tile,
     }
 }
 
-template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS>
+// MODE 0: one problem, tile = f(blockIdx) (A/B; kernel boundary between
+//         trips is the only synchronization).
+// MODE 1: one problem, tiles from a ticket counter, progress flags
+//         (compressed single grid).
+// MODE 2: a batch of independent problems described by p.table; tiles of all
+//         problems from one ticket counter; A/B parity read from *p.parity.
+template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE>
 __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 {
+    constexpr bool FLAGS = MODE == 1;
     constexpr int H = R * W;
     constexpr int OX = 64 - 2 * T;
     constexpr int OY = H - 2 * T;
@@ -390,7 +407,7 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 
     for (int iter = 0;; ++iter) {
         int tile;
-        if (!FLAGS) {
+        if (MODE == 0) {
             if (iter > 0) return;
             tile = xcd_tile(blockIdx.x, p.ntiles);
         } else {
@@ -399,17 +416,58 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             __syncthreads();
             const int t = tile_sh;
             if (t >= p.ntiles) return;
-            tile = p.dir > 0 ? t : p.ntiles - 1 - t;
+            tile = (MODE == 1 && p.dir < 0) ? p.ntiles - 1 - t : t;
         }
-        const int tx = tile % p.tiles_x;
-        const int ty = (tile / p.tiles_x) % p.tiles_y;
+        Geo g;
+        if (MODE == 2) {
+            int lo = 0, hi = p.count - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (p.table[mid].tile_base <= tile)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const BatchProblem& bp = p.table[lo];
+            const int par = *p.parity & 1;
+            g.src = bp.grid[par];
+            g.dst = bp.grid[par ^ 1];
+            g.rhs = bp.rhs;
+            g.px = g.rpx = bp.px;
+            g.py = g.rpy = bp.py;
+            g.nx = bp.nx;
+            g.ny = bp.ny;
+            g.nz = bp.nz;
+            g.tiles_x = bp.tiles_x;
+            g.tiles_y = bp.tiles_y;
+            g.segs = bp.segs;
+            g.seg_len = bp.seg_len;
+            tile -= bp.tile_base;
+        } else {
+            g.src = p.src;
+            g.dst = p.dst;
+            g.rhs = p.rhs;
+            g.px = p.px;
+            g.py = p.py;
+            g.rpx = p.rpx;
+            g.rpy = p.rpy;
+            g.nx = p.nx;
+            g.ny = p.ny;
+            g.nz = p.nz;
+            g.tiles_x = p.tiles_x;
+            g.tiles_y = p.tiles_y;
+            g.segs = p.segs;
+            g.seg_len = p.seg_len;
+        }
+        const int tx = tile % g.tiles_x;
+        const int ty = (tile / g.tiles_x) % g.tiles_y;
         const int ilo = tx * OX - T, jlo = ty * OY - T;
-        const bool interior_tile = ilo >= 1 && ilo + 63 <= p.nx && jlo >= 1 &&
-                                   jlo + H - 1 <= p.ny;
+        const bool interior_tile = ilo >= 1 && ilo + 63 <= g.nx && jlo >= 1 &&
+                                   jlo + H - 1 <= g.ny;
         if (interior_tile)
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, false>(p, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, false>(p, g, tile, xch);
         else
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, true>(p, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, true>(p, g, tile, xch);
     }
 }
 
@@ -418,22 +476,34 @@ hipError_t launch_cfg(const TripParams& p, hipStream_t s)
 {
     dim3 block(64 * W);
     if (p.mode == 0) {
-        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, false>),
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 0>),
                            dim3(p.ntiles), block, 0, s, p);
-    } else {
-        int dev = 0, cus = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        int per_cu = 0;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(
-                         &trip_kernel<Real, T, R, W, PF, RHS, true>),
-            64 * W, 0);
-        int grid = cus * (per_cu > 0 ? per_cu : 1);
-        if (grid > p.ntiles) grid = p.ntiles;
-        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, true>), dim3(grid),
-                           block, 0, s, p);
+        return hipGetLastError();
     }
+    // Persistent launch: as many workgroups as can be resident.
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = p.mode == 1
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, reinterpret_cast<const void*>(
+                                   &trip_kernel<Real, T, R, W, PF, RHS, 1>),
+                      64 * W, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, reinterpret_cast<const void*>(
+                                   &trip_kernel<Real, T, R, W, PF, RHS, 2>),
+                      64 * W, 0);
+    if (e != hipSuccess) return e;
+    int grid = cus * (per_cu > 0 ? per_cu : 1);
+    if (grid > p.ntiles) grid = p.ntiles;
+    if (p.mode == 1)
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 1>), dim3(grid),
+                           block, 0, s, p);
+    else
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 2>), dim3(grid),
+                           block, 0, s, p);
     return hipGetLastError();
 }
 
@@ -477,7 +547,7 @@ hipError_t launch_trip_f64(const TripConfig& c, const TripParams& p,
 hipError_t launch_trip_f32(const TripConfig& c, const TripParams& p,
                            hipStream_t s)
 {
-    if (p.rhs) return dispatch<float, true>(c, p, s);
+    if (p.rhs || p.rhs_in_table) return dispatch<float, true>(c, p, s);
     return dispatch<float, false>(c, p, s);
 }
 
