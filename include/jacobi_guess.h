@@ -1,0 +1,77 @@
+/*
+ * jacobi_guess.h -- C-ABI of the learned initial guess for the Jacobi solver
+ * of jacobi.h (libjacobi, gfx950).
+ *
+ * The Jacobi method (Sect. 1.1 of Wittmann et al. 2010) converges from any
+ * starting field; this network maps the six boundary faces of an n^3 problem
+ * to a starting interior field, trained on converged solutions produced by
+ * the solver.  The network is a small 3D U-Net:
+ *   - input: 16 channels per interior cell = the six face values at the
+ *     cell's projections (faces i=0, i=n+1, j=0, j=n+1, k=0, k=n+1), the
+ *     three centred coordinates x/(n+1) - 1/2, and 7 zeros;
+ *   - `levels` resolutions n, n/2, ...; per encoder level two 3x3x3 conv +
+ *     ReLU, then a stride-2 3x3x3 conv + ReLU down; per decoder level a
+ *     nearest x2 upsampling added to the encoder output of that level, then
+ *     two 3x3x3 conv + ReLU; a 1x1x1 head to one output channel;
+ *   - 16 channels everywhere, zero padding, BF16 weights and activations,
+ *     FP32 accumulation (MFMA), FP32 master parameters and gradients.
+ * Flat FP32 parameter vector, in this order: for every conv layer (enc0_a,
+ * enc0_b, down0, enc1_a, ..., enc{L-1}_b, dec{L-2}_a, dec{L-2}_b, ...,
+ * dec0_b) its weights [27][Cout][Cin] (tap t = (dz+1)*9 + (dy+1)*3 + (dx+1))
+ * then its 16 biases; then the head's 16 weights and 1 bias.
+ *
+ * All device buffers are caller-owned.  Functions return 0 or a negative
+ * jacobi_status (jacobi.h) and never abort; launches are asynchronous on the
+ * stream given at creation.
+ */
+#ifndef JACOBI_GUESS_H
+#define JACOBI_GUESS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jg_net_s jg_net;
+
+/* Number of FP32 parameters of a `levels`-level network (levels 2..6). */
+int jg_param_count(int32_t levels, int64_t *count);
+
+/* Workspace bytes for edge n (n divisible by 2^(levels-1), n >= 2^(levels-1)). */
+int jg_workspace_size(int64_t n, int32_t levels, size_t *bytes);
+
+/* params, grads, adam_m, adam_v: device FP32 vectors of jg_param_count
+ * entries (grads/m/v may be NULL for inference only).  workspace: 256-byte
+ * aligned device memory of jg_workspace_size bytes. */
+int jg_create(int64_t n, int32_t levels, float *params, float *grads,
+              float *adam_m, float *adam_v, void *workspace,
+              size_t workspace_bytes, void *stream, jg_net **out);
+
+/* Forward pass on a dense (n+2)^3 FP64 box (only its faces are read).
+ * `out` (n^3 FP32, may be NULL) receives the network output. */
+int jg_forward(jg_net *h, const double *box, float *out);
+
+/* After jg_forward: MSE loss against `target` (n^3 FP32) and backward pass;
+ * parameter gradients are ADDED to `grads`.  If `loss` is non-NULL the
+ * stream is synchronized and the loss written to it. */
+int jg_backward(jg_net *h, const float *target, double *loss);
+
+int jg_zero_grads(jg_net *h);
+
+/* Adam step on params with grads (bias-corrected, step >= 1). */
+int jg_adam(jg_net *h, float lr, float beta1, float beta2, float eps,
+            int64_t step);
+
+/* Writes the last forward output into the interior of a dense (n+2)^3 FP64
+ * box (the solver's initial field); the boundary is left untouched. */
+int jg_write_guess(jg_net *h, double *box);
+
+int jg_destroy(jg_net *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JACOBI_GUESS_H */

@@ -1,0 +1,602 @@
+// Kernels of the learned initial guess (a small 3D U-Net) for gfx950.
+//
+// The guess only supplies the starting field of the Jacobi method (Sect. 1.1
+// of the paper); the paper itself starts from a fixed field.  Numerics: BF16
+// weights and activations, FP32 accumulation on MFMA, FP32 gradients.
+//
+// Layouts: activations [D][H][W][16] bfloat16 (channel last, 32 B per voxel);
+// activation gradients [D][H][W][16] float; conv weights [27][Cout][Cin]
+// bfloat16 with tap t = (dz+1)*9 + (dy+1)*3 + (dx+1) and a transposed copy
+// [27][Cin][Cout] for the data gradient.
+//
+// 3x3x3 convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: one wave
+// computes a 16 (voxels along x) x 16 (channels) output tile and accumulates
+// 27 taps x 16 input channels.  Operand lane layout of the 16x16x16 MFMA: lane
+// l holds A[m = l%16][k = 4(l/16) .. 4(l/16)+3], B[k = 4(l/16)..+3][n = l%16]
+// and receives D[m = 4(l/16)+i][n = l%16], i = 0..3.
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "nn_internal.h"
+
+namespace jacobi_impl {
+namespace nn {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b)
+{
+    return __uint_as_float((uint32_t)b << 16);
+}
+
+__device__ __forceinline__ v4s load4bf(const uint16_t* p)
+{
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    v4s r;
+    r[0] = (short)(v.x & 0xffff);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xffff);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+__device__ __forceinline__ v4s f4_to_bf(const float* p)
+{
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    v4s r;
+    r[0] = (short)f2bf(v.x);
+    r[1] = (short)f2bf(v.y);
+    r[2] = (short)f2bf(v.z);
+    r[3] = (short)f2bf(v.w);
+    return r;
+}
+
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- lift ----
+// x[k][j][i][c] for the interior of an (n+2)^3 FP64 box: six face values,
+// three centred coordinates, zeros.
+__global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ box,
+                                                   int n, uint16_t* __restrict__ x)
+{
+    const int64_t nv = (int64_t)n * n * n;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / ((int64_t)n * n));
+    const int64_t p = n + 2, pp = p * p;
+    const int64_t kk = k + 1, jj = j + 1, ii = i + 1;
+    float c[16];
+    c[0] = (float)box[kk * pp + jj * p + 0];
+    c[1] = (float)box[kk * pp + jj * p + (n + 1)];
+    c[2] = (float)box[kk * pp + 0 * p + ii];
+    c[3] = (float)box[kk * pp + (int64_t)(n + 1) * p + ii];
+    c[4] = (float)box[0 * pp + jj * p + ii];
+    c[5] = (float)box[(int64_t)(n + 1) * pp + jj * p + ii];
+    c[6] = (float)((double)(i + 1) / (n + 1) - 0.5);
+    c[7] = (float)((double)(j + 1) / (n + 1) - 0.5);
+    c[8] = (float)((double)(k + 1) / (n + 1) - 0.5);
+#pragma unroll
+    for (int q = 9; q < 16; ++q) c[q] = 0.f;
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        w[q] = (uint32_t)f2bf(c[2 * q]) | ((uint32_t)f2bf(c[2 * q + 1]) << 16);
+    uint4* dst = reinterpret_cast<uint4*>(x + v * 16);
+    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+// ------------------------------------------------------ conv forward ----
+// y[o] = relu?(b + sum_t W_t x[S*o + d_t]); input D^3 (Din), output Dout^3.
+template <int S, bool RELU>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(
+    const uint16_t* __restrict__ x, int din, const uint16_t* __restrict__ w,
+    const float* __restrict__ bias, uint16_t* __restrict__ y, int dout)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
+    const int xt = (dout + 15) >> 4;
+    const int64_t ntile = (int64_t)dout * dout * xt;
+    if (wid >= ntile) return;
+    const int ox0 = (wid % xt) * 16;
+    const int oy = (wid / xt) % dout;
+    const int oz = wid / (xt * dout);
+    const int m = lane & 15, kq = lane >> 4;
+    const int ox = ox0 + m;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const int iz = S * oz + dz, iy = S * oy + dy, ix = S * ox + dx;
+        v4s a = {0, 0, 0, 0};
+        if (ox < dout && (unsigned)iz < (unsigned)din && (unsigned)iy < (unsigned)din &&
+            (unsigned)ix < (unsigned)din)
+            a = load4bf(x + (((int64_t)iz * din + iy) * din + ix) * 16 + 4 * kq);
+        const v4s bw = load4bf(w + ((int64_t)t * 16 + m) * 16 + 4 * kq);
+        acc = mfma16(a, bw, acc);
+    }
+    const int n = lane & 15;
+    const float bn = bias[n];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int vx = ox0 + 4 * kq + r;
+        if (vx >= dout) continue;
+        float v = acc[r] + bn;
+        if (RELU) v = fmaxf(v, 0.f);
+        y[(((int64_t)oz * dout + oy) * dout + vx) * 16 + n] = f2bf(v);
+    }
+}
+
+// ---------------------------------------------------- conv data grad ----
+// dx[v] (+)= sum_t W_t^T dy[(v - d_t)/S] over the taps with an integral
+// in-range source; then dx *= (mask[v] > 0) if a mask (the ReLU output that
+// produced this conv's input) is given.  wt: [27][Cin][Cout].
+template <int S>
+__global__ __launch_bounds__(256) void conv_bwd_data_kernel(
+    const float* __restrict__ dy, int dout, const uint16_t* __restrict__ wt,
+    float* __restrict__ dx, int din, int accum, const uint16_t* __restrict__ mask)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
+    const int xt = (din + 15) >> 4;
+    const int64_t ntile = (int64_t)din * din * xt;
+    if (wid >= ntile) return;
+    const int vx0 = (wid % xt) * 16;
+    const int vy = (wid / xt) % din;
+    const int vz = wid / (xt * din);
+    const int m = lane & 15, kq = lane >> 4;
+    const int vx = vx0 + m;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx_ = t % 3 - 1;
+        int oz = vz - dz, oy = vy - dyy, ox = vx - dx_;
+        bool ok = vx < din;
+        if (S == 2) {
+            ok = ok && !(oz & 1) && !(oy & 1) && !(ox & 1);
+            oz >>= 1;
+            oy >>= 1;
+            ox >>= 1;
+        }
+        ok = ok && (unsigned)oz < (unsigned)dout && (unsigned)oy < (unsigned)dout &&
+             (unsigned)ox < (unsigned)dout;
+        v4s a = {0, 0, 0, 0};
+        if (ok) a = f4_to_bf(dy + (((int64_t)oz * dout + oy) * dout + ox) * 16 + 4 * kq);
+        const v4s bw = load4bf(wt + ((int64_t)t * 16 + m) * 16 + 4 * kq);
+        acc = mfma16(a, bw, acc);
+    }
+    const int n = lane & 15;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int x = vx0 + 4 * kq + r;
+        if (x >= din) continue;
+        const int64_t idx = (((int64_t)vz * din + vy) * din + x) * 16 + n;
+        float v = acc[r];
+        if (accum) v += dx[idx];
+        if (mask && !(bf2f(mask[idx]) > 0.f)) v = 0.f;
+        dx[idx] = v;
+    }
+}
+
+// -------------------------------------------------- conv weight grad ----
+// Per block: partial dw[t][co][ci] = sum over its output voxels o of
+// dy[o][co] * x[S*o + d_t][ci], and partial db[co] = sum dy[o][co].
+// Voxels are taken 16 at a time by each wave (the K dimension of the MFMA).
+template <int S>
+__global__ __launch_bounds__(256) void conv_bwd_weight_kernel(
+    const uint16_t* __restrict__ x, int din, const float* __restrict__ dy,
+    int dout, float* __restrict__ part, int chunks_per_wave)
+{
+    __shared__ float red[4][27 * 256 + 16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int64_t nvox = (int64_t)dout * dout * dout;
+    const int64_t nchunk = (nvox + 15) / 16;
+    v4f acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+    float dbs = 0.f;
+    const int64_t first = ((int64_t)blockIdx.x * 4 + wave) * chunks_per_wave;
+    for (int c = 0; c < chunks_per_wave; ++c) {
+        const int64_t ch = first + c;
+        if (ch >= nchunk) break;
+        // A[m = co][k = voxel 4kq..4kq+3] = dy[voxel][co]
+        int oz[4], oy[4], ox[4];
+        bool ov[4];
+        v4s a;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t o = ch * 16 + 4 * kq + r;
+            ov[r] = o < nvox;
+            const int64_t oc = ov[r] ? o : 0;
+            ox[r] = (int)(oc % dout);
+            oy[r] = (int)((oc / dout) % dout);
+            oz[r] = (int)(oc / ((int64_t)dout * dout));
+            const float g = ov[r] ? dy[oc * 16 + m] : 0.f;
+            dbs += g;
+            a[r] = (short)f2bf(g);
+        }
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx_ = t % 3 - 1;
+            v4s b;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int iz = S * oz[r] + dz, iy = S * oy[r] + dyy, ix = S * ox[r] + dx_;
+                uint16_t v = 0;
+                if (ov[r] && (unsigned)iz < (unsigned)din && (unsigned)iy < (unsigned)din &&
+                    (unsigned)ix < (unsigned)din)
+                    v = x[(((int64_t)iz * din + iy) * din + ix) * 16 + m];
+                b[r] = (short)v;
+            }
+            acc[t] = mfma16(a, b, acc[t]);
+        }
+    }
+    // D[m = co 4kq+r][n = ci lane%16] -> red[wave][t*256 + co*16 + ci]
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave][t * 256 + (4 * kq + r) * 16 + m] = acc[t][r];
+    // db: lanes with the same m (co) hold partial sums; reduce over kq
+    dbs += __shfl_xor(dbs, 16, 64);
+    dbs += __shfl_xor(dbs, 32, 64);
+    if (lane < 16) red[wave][27 * 256 + lane] = dbs;
+    __syncthreads();
+    for (int q = threadIdx.x; q < 27 * 256 + 16; q += blockDim.x)
+        part[(int64_t)blockIdx.x * (27 * 256 + 16) + q] =
+            ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+}
+
+// Sum of per-block partials (fixed order) added into the FP32 gradient.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(
+    const float* __restrict__ part, int blocks, int width, float* __restrict__ grad)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= width) return;
+    float s = 0.f;
+    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * width + q];
+    grad[q] += s;
+}
+
+// ----------------------------------------------------- up / skip add ----
+// s[v] = bf16(x[v/2] + skip[v]) on a D^3 grid (x is (D/2)^3).
+__global__ __launch_bounds__(256) void up_add_kernel(
+    const uint16_t* __restrict__ x, const uint16_t* __restrict__ skip,
+    uint16_t* __restrict__ s, int d)
+{
+    const int64_t n = (int64_t)d * d * d * 16;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int c = (int)(q & 15);
+    const int64_t v = q >> 4;
+    const int i = (int)(v % d), j = (int)((v / d) % d), k = (int)(v / ((int64_t)d * d));
+    const int h = d / 2;
+    const int64_t src = ((((int64_t)(k >> 1) * h + (j >> 1)) * h + (i >> 1)) << 4) + c;
+    s[q] = f2bf(bf2f(x[src]) + bf2f(skip[q]));
+}
+
+// dx[o] = mask? * sum of the 8 children of o in ds (D^3 -> (D/2)^3).
+__global__ __launch_bounds__(256) void up_bwd_kernel(const float* __restrict__ ds,
+                                                     float* __restrict__ dx, int d,
+                                                     const uint16_t* __restrict__ mask)
+{
+    const int h = d / 2;
+    const int64_t n = (int64_t)h * h * h * 16;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int c = (int)(q & 15);
+    const int64_t v = q >> 4;
+    const int i = (int)(v % h), j = (int)((v / h) % h), k = (int)(v / ((int64_t)h * h));
+    float s = 0.f;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx)
+                s += ds[((((int64_t)(2 * k + cz) * d + (2 * j + cy)) * d + (2 * i + cx)) << 4) + c];
+    if (mask && !(bf2f(mask[q]) > 0.f)) s = 0.f;
+    dx[q] = s;
+}
+
+// ------------------------------------------------------------- head ----
+// out = hw . x + hb (FP32).  With a target: per-block partial sums of
+// (out - target)^2 and dout = 2 (out - target) / nvox written to dx as
+// dx[v][c] = dout * hw[c] (masked by x > 0), and per-block partials of
+// dhw[c] = sum dout x[c], dhb = sum dout.
+__global__ __launch_bounds__(256) void head_kernel(
+    const uint16_t* __restrict__ x, int64_t nvox, const float* __restrict__ hw,
+    const float* __restrict__ hb, float* __restrict__ out,
+    const float* __restrict__ target, float* __restrict__ dx,
+    double* __restrict__ loss_part, float* __restrict__ gpart)
+{
+    __shared__ double sl[256];
+    __shared__ float sg[17][256];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float xc[16];
+    float o = 0.f;
+    if (v < nvox) {
+        const uint4* src = reinterpret_cast<const uint4*>(x + v * 16);
+        const uint4 a = src[0], b = src[1];
+        const uint32_t wds[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            xc[2 * q] = bf2f((uint16_t)(wds[q] & 0xffff));
+            xc[2 * q + 1] = bf2f((uint16_t)(wds[q] >> 16));
+        }
+        o = hb[0];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) o += hw[c] * xc[c];
+        if (out) out[v] = o;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) xc[c] = 0.f;
+    }
+    if (!target) return;
+    double l = 0.0;
+    float g = 0.f;
+    if (v < nvox) {
+        const float diff = o - target[v];
+        l = (double)diff * diff;
+        g = 2.f * diff / (float)nvox;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            dx[v * 16 + c] = (xc[c] > 0.f) ? g * hw[c] : 0.f;
+    }
+    sl[threadIdx.x] = l;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) sg[c][threadIdx.x] = g * xc[c];
+    sg[16][threadIdx.x] = g;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sl[threadIdx.x] += sl[threadIdx.x + s];
+#pragma unroll
+            for (int c = 0; c < 17; ++c) sg[c][threadIdx.x] += sg[c][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        loss_part[blockIdx.x] = sl[0];
+        for (int c = 0; c < 17; ++c) gpart[(int64_t)blockIdx.x * 17 + c] = sg[c][0];
+    }
+}
+
+__global__ __launch_bounds__(256) void sum_loss_kernel(const double* __restrict__ part,
+                                                       int n, int64_t nvox,
+                                                       double* __restrict__ out)
+{
+    __shared__ double s[256];
+    double a = 0.0;
+    for (int q = threadIdx.x; q < n; q += 256) a += part[q];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0] / (double)nvox;
+}
+
+// Output (FP32, n^3) into the interior of an (n+2)^3 FP64 box.
+__global__ __launch_bounds__(256) void write_guess_kernel(const float* __restrict__ out,
+                                                          int n, double* __restrict__ box)
+{
+    const int64_t nv = (int64_t)n * n * n;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / ((int64_t)n * n));
+    const int64_t p = n + 2;
+    box[((int64_t)(k + 1) * p + (j + 1)) * p + (i + 1)] = (double)out[v];
+}
+
+// --------------------------------------------------- parameters / Adam ----
+// bf16 copies of every conv layer's weights: w[l][t][co][ci] and the
+// transpose wt[l][t][ci][co], from the FP32 parameter vector.
+__global__ __launch_bounds__(256) void prep_weights_kernel(
+    const float* __restrict__ params, const int64_t* __restrict__ woff, int layers,
+    uint16_t* __restrict__ w, uint16_t* __restrict__ wt)
+{
+    const int64_t per = 27 * 256;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= per * layers) return;
+    const int l = (int)(q / per);
+    const int r = (int)(q % per);
+    const int t = r / 256, co = (r / 16) % 16, ci = r % 16;
+    const uint16_t b = f2bf(params[woff[l] + r]);
+    w[q] = b;
+    wt[(int64_t)l * per + t * 256 + ci * 16 + co] = b;
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p,
+                                                   const float* __restrict__ g,
+                                                   float* __restrict__ m,
+                                                   float* __restrict__ v, int64_t n,
+                                                   float lr, float b1, float b2, float eps,
+                                                   float c1, float c2)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.f - b1) * gq;
+    const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+        p[q] = 0.f;
+}
+
+// Head parameter gradients from per-block partials (fixed order).
+__global__ void head_grad_kernel(const float* __restrict__ gpart, int blocks,
+                                 float* __restrict__ ghw, float* __restrict__ ghb)
+{
+    const int c = threadIdx.x;
+    if (c >= 17) return;
+    float s = 0.f;
+    for (int b = 0; b < blocks; ++b) s += gpart[(int64_t)b * 17 + c];
+    if (c < 16)
+        ghw[c] += s;
+    else
+        ghb[0] += s;
+}
+
+int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t lift(const double* box, int n, uint16_t* x, hipStream_t s)
+{
+    const int64_t nv = (int64_t)n * n * n;
+    hipLaunchKernelGGL(lift_kernel, dim3(blocks_for(nv, 256)), dim3(256), 0, s, box, n, x);
+    return hipGetLastError();
+}
+
+hipError_t conv_fwd(const uint16_t* x, int din, const uint16_t* w, const float* b,
+                    uint16_t* y, int stride, bool relu, hipStream_t s)
+{
+    const int dout = din / stride;
+    const int64_t tiles = (int64_t)dout * dout * ((dout + 15) / 16);
+    const dim3 grid(blocks_for(tiles, 4));
+    if (stride == 1) {
+        if (relu)
+            hipLaunchKernelGGL((conv_fwd_kernel<1, true>), grid, dim3(256), 0, s, x, din, w, b, y, dout);
+        else
+            hipLaunchKernelGGL((conv_fwd_kernel<1, false>), grid, dim3(256), 0, s, x, din, w, b, y, dout);
+    } else {
+        if (relu)
+            hipLaunchKernelGGL((conv_fwd_kernel<2, true>), grid, dim3(256), 0, s, x, din, w, b, y, dout);
+        else
+            hipLaunchKernelGGL((conv_fwd_kernel<2, false>), grid, dim3(256), 0, s, x, din, w, b, y, dout);
+    }
+    return hipGetLastError();
+}
+
+hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* wt, float* dx,
+                         int din, int stride, bool accum, const uint16_t* mask,
+                         hipStream_t s)
+{
+    const int64_t tiles = (int64_t)din * din * ((din + 15) / 16);
+    const dim3 grid(blocks_for(tiles, 4));
+    if (stride == 1)
+        hipLaunchKernelGGL((conv_bwd_data_kernel<1>), grid, dim3(256), 0, s, dy, dout, wt, dx,
+                           din, accum ? 1 : 0, mask);
+    else
+        hipLaunchKernelGGL((conv_bwd_data_kernel<2>), grid, dim3(256), 0, s, dy, dout, wt, dx,
+                           din, accum ? 1 : 0, mask);
+    return hipGetLastError();
+}
+
+int wgrad_blocks(int dout)
+{
+    const int64_t nchunk = ((int64_t)dout * dout * dout + 15) / 16;
+    int64_t b = (nchunk + 4 * 8 - 1) / (4 * 8);  // >= 8 chunks per wave
+    if (b > 512) b = 512;
+    return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t conv_bwd_weight(const uint16_t* x, int din, const float* dy, int dout,
+                           int stride, float* part, float* grad_w_b, hipStream_t s)
+{
+    const int blocks = wgrad_blocks(dout);
+    const int64_t nchunk = ((int64_t)dout * dout * dout + 15) / 16;
+    const int cpw = (int)((nchunk + (int64_t)blocks * 4 - 1) / ((int64_t)blocks * 4));
+    if (stride == 1)
+        hipLaunchKernelGGL((conv_bwd_weight_kernel<1>), dim3(blocks), dim3(256), 0, s, x, din,
+                           dy, dout, part, cpw);
+    else
+        hipLaunchKernelGGL((conv_bwd_weight_kernel<2>), dim3(blocks), dim3(256), 0, s, x, din,
+                           dy, dout, part, cpw);
+    const int width = 27 * 256 + 16;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(width, 256)), dim3(256), 0, s,
+                       part, blocks, width, grad_w_b);
+    return hipGetLastError();
+}
+
+hipError_t up_add(const uint16_t* x, const uint16_t* skip, uint16_t* out, int d,
+                  hipStream_t s)
+{
+    const int64_t n = (int64_t)d * d * d * 16;
+    hipLaunchKernelGGL(up_add_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, skip, out, d);
+    return hipGetLastError();
+}
+
+hipError_t up_bwd(const float* ds, float* dx, int d, const uint16_t* mask, hipStream_t s)
+{
+    const int64_t n = (int64_t)(d / 2) * (d / 2) * (d / 2) * 16;
+    hipLaunchKernelGGL(up_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, ds, dx, d, mask);
+    return hipGetLastError();
+}
+
+int head_blocks(int64_t nvox) { return blocks_for(nvox, 256); }
+
+hipError_t head(const uint16_t* x, int64_t nvox, const float* hw, const float* hb,
+                float* out, const float* target, float* dx, double* loss_part,
+                float* gpart, double* loss, float* ghw, float* ghb, hipStream_t s)
+{
+    const int blocks = head_blocks(nvox);
+    hipLaunchKernelGGL(head_kernel, dim3(blocks), dim3(256), 0, s, x, nvox, hw, hb, out,
+                       target, dx, loss_part, gpart);
+    if (target) {
+        hipLaunchKernelGGL(sum_loss_kernel, dim3(1), dim3(256), 0, s, loss_part, blocks, nvox,
+                           loss);
+        hipLaunchKernelGGL(head_grad_kernel, dim3(1), dim3(64), 0, s, gpart, blocks, ghw, ghb);
+    }
+    return hipGetLastError();
+}
+
+hipError_t write_guess(const float* out, int n, double* box, hipStream_t s)
+{
+    const int64_t nv = (int64_t)n * n * n;
+    hipLaunchKernelGGL(write_guess_kernel, dim3(blocks_for(nv, 256)), dim3(256), 0, s, out, n,
+                       box);
+    return hipGetLastError();
+}
+
+hipError_t prep_weights(const float* params, const int64_t* woff, int layers, uint16_t* w,
+                        uint16_t* wt, hipStream_t s)
+{
+    const int64_t n = (int64_t)27 * 256 * layers;
+    hipLaunchKernelGGL(prep_weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, params,
+                       woff, layers, w, wt);
+    return hipGetLastError();
+}
+
+hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                float b2, float eps, int64_t step, hipStream_t s)
+{
+    const float c1 = 1.f - powf(b1, (float)step);
+    const float c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, g, m, v, n,
+                       lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t zero_f32(float* p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int g = blocks_for(n, 256);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(g), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace nn
+}  // namespace jacobi_impl

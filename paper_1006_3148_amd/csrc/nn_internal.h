@@ -1,0 +1,39 @@
+// Internal launchers of the learned-guess network kernels (kernels_nn.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jacobi_impl {
+namespace nn {
+
+constexpr int kC = 16;                      // channels
+constexpr int64_t kConvW = 27 * kC * kC;    // weights per conv layer
+constexpr int64_t kConvP = kConvW + kC;     // weights + bias per conv layer
+
+hipError_t lift(const double* box, int n, uint16_t* x, hipStream_t s);
+hipError_t conv_fwd(const uint16_t* x, int din, const uint16_t* w, const float* b,
+                    uint16_t* y, int stride, bool relu, hipStream_t s);
+hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* wt, float* dx,
+                         int din, int stride, bool accum, const uint16_t* mask,
+                         hipStream_t s);
+int wgrad_blocks(int dout);
+hipError_t conv_bwd_weight(const uint16_t* x, int din, const float* dy, int dout,
+                           int stride, float* part, float* grad_w_b, hipStream_t s);
+hipError_t up_add(const uint16_t* x, const uint16_t* skip, uint16_t* out, int d,
+                  hipStream_t s);
+hipError_t up_bwd(const float* ds, float* dx, int d, const uint16_t* mask,
+                  hipStream_t s);
+int head_blocks(int64_t nvox);
+hipError_t head(const uint16_t* x, int64_t nvox, const float* hw, const float* hb,
+                float* out, const float* target, float* dx, double* loss_part,
+                float* gpart, double* loss, float* ghw, float* ghb, hipStream_t s);
+hipError_t write_guess(const float* out, int n, double* box, hipStream_t s);
+hipError_t prep_weights(const float* params, const int64_t* woff, int layers,
+                        uint16_t* w, uint16_t* wt, hipStream_t s);
+hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                float b1, float b2, float eps, int64_t step, hipStream_t s);
+hipError_t zero_f32(float* p, int64_t n, hipStream_t s);
+
+}  // namespace nn
+}  // namespace jacobi_impl

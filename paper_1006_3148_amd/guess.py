@@ -1,0 +1,104 @@
+"""Python handle over the learned-guess C-ABI (jacobi_guess.h): marshalling
+only; every step runs in libjacobi's kernels."""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import check, lib
+
+_h = ctypes.c_void_p
+_SIGS = {
+    "jg_param_count": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "jg_workspace_size": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+                          ctypes.c_int),
+    "jg_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                   ctypes.c_void_p, ctypes.POINTER(_h)], ctypes.c_int),
+    "jg_forward": ([_h, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "jg_backward": ([_h, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "jg_zero_grads": ([_h], ctypes.c_int),
+    "jg_adam": ([_h, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                 ctypes.c_int64], ctypes.c_int),
+    "jg_write_guess": ([_h, ctypes.c_void_p], ctypes.c_int),
+    "jg_destroy": ([_h], ctypes.c_int),
+}
+for _name, (_a, _r) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _a
+    _f.restype = _r
+
+EXPORTED = tuple(_SIGS)
+
+
+def param_count(levels: int) -> int:
+    c = ctypes.c_int64()
+    check(lib.jg_param_count(levels, ctypes.byref(c)))
+    return c.value
+
+
+class GuessNet:
+    """The U-Net on the GPU.  ``params`` (numpy FP32/FP64 vector) initialises
+    the FP32 master parameters; gradients and Adam moments are allocated
+    here (torch tensors)."""
+
+    def __init__(self, n: int, levels: int, params, train: bool = True,
+                 stream=None, device: str = "cuda"):
+        self.n, self.levels = n, levels
+        self.np_ = param_count(levels)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        p = np.asarray(params, dtype=np.float32)
+        if p.size != self.np_:
+            raise ValueError("expected %d parameters, got %d" % (self.np_, p.size))
+        ws = ctypes.c_size_t()
+        check(lib.jg_workspace_size(n, levels, ctypes.byref(ws)))
+        with torch.cuda.stream(self.stream):
+            self.params = torch.from_numpy(p.copy()).to(device)
+            self.grads = torch.zeros_like(self.params) if train else None
+            self.m = torch.zeros_like(self.params) if train else None
+            self.v = torch.zeros_like(self.params) if train else None
+            self.ws = torch.empty(ws.value, dtype=torch.uint8, device=device)
+            self.out = torch.empty(n ** 3, dtype=torch.float32, device=device)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        ptr = (lambda t: t.data_ptr() if t is not None else None)
+        check(lib.jg_create(n, levels, ptr(self.params), ptr(self.grads), ptr(self.m),
+                            ptr(self.v), self.ws.data_ptr(), self.ws.numel(),
+                            int(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.step_count = 0
+
+    def forward(self, box: torch.Tensor) -> torch.Tensor:
+        """box: dense (n+2)^3 float64 CUDA tensor; returns the n^3 output."""
+        check(lib.jg_forward(self._h, box.data_ptr(), self.out.data_ptr()))
+        return self.out.view(self.n, self.n, self.n)
+
+    def backward(self, target: torch.Tensor, want_loss: bool = True):
+        loss = ctypes.c_double()
+        check(lib.jg_backward(self._h, target.data_ptr(),
+                              ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def zero_grads(self) -> None:
+        check(lib.jg_zero_grads(self._h))
+
+    def adam(self, lr: float, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+        self.step_count += 1
+        check(lib.jg_adam(self._h, lr, beta1, beta2, eps, self.step_count))
+
+    def write_guess(self, box: torch.Tensor) -> None:
+        check(lib.jg_write_guess(self._h, box.data_ptr()))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.jg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

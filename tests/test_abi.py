@@ -6,24 +6,44 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "jacobi.h")).read()
+def _declared(header, prefix):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(jacobi_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(%s[a-z_0-9]+)\s*\(" % prefix, src)))
 
 
 def test_library_exports_every_declared_symbol():
     import paper_1006_3148_amd as pkg
-    names = _declared()
-    assert "jacobi_create" in names and "jacobi_sweep" in names
+    from paper_1006_3148_amd import guess
+    names = _declared("jacobi.h", "jacobi_")
+    assert "jacobi_create" in names and "jacobi_batch_sweep" in names
     for n in names:
         assert hasattr(pkg.lib, n), n
     assert set(names) == set(pkg._lib.EXPORTED)
+    gnames = _declared("jacobi_guess.h", "jg_")
+    assert "jg_forward" in gnames
+    for n in gnames:
+        assert hasattr(pkg.lib, n), n
+    assert set(gnames) == set(guess.EXPORTED)
+
+
+def test_guess_sizes_and_errors():
+    from paper_1006_3148_amd import lib, param_count
+    from oracle import conv as cv
+    for L in (2, 3, 4):
+        assert param_count(L) == sum(int(np.prod(s)) for _, s in cv.param_shapes(L))
+    n = ctypes.c_size_t()
+    assert lib.jg_workspace_size(12, 4, ctypes.byref(n)) == -1   # 12 % 8 != 0
+    assert lib.jg_workspace_size(16, 7, ctypes.byref(n)) == -1   # levels
+    assert lib.jg_workspace_size(16, 4, ctypes.byref(n)) == 0 and n.value > 0
+    h = ctypes.c_void_p()
+    assert lib.jg_create(16, 4, None, None, None, None, None, 0, None, ctypes.byref(h)) == -1
 
 
 def _desc(**kw):
