@@ -185,6 +185,15 @@ int jacobi_batch_sweep(jacobi_batch_t *h, int64_t n_steps);
 /* Per-problem residual norms (and optional max |r|), host arrays [count];
  * synchronizes. */
 int jacobi_batch_residual(jacobi_batch_t *h, double *l2, double *maxabs);
+/* Sweeps every problem until each has ||r_q|| <= rel_tol * r0[q] (r0 NULL or
+ * r0[q] <= 0: the problem's current residual), checking every check_every
+ * sweeps, at most max_sweeps.  sweeps_done[q] = sweeps at the first check
+ * where problem q met its tolerance (-1 if it never did); final_l2[q] = its
+ * residual then (or at the end).  Problems that converged keep being swept
+ * until all have (their reported counts are not affected). */
+int jacobi_batch_solve(jacobi_batch_t *h, double rel_tol, const double *r0,
+                       int64_t max_sweeps, int64_t check_every,
+                       int64_t *sweeps_done, double *final_l2);
 int jacobi_batch_current(jacobi_batch_t *h, int32_t i, void **origin,
                          int64_t strides[3]);
 /* Sweeps done, chosen configuration, and the time spent tuning (ms). */

@@ -10,7 +10,7 @@ machine where ``libjacobi.so`` is missing raises ``ImportError``.
 from ._lib import lib, LIB_PATH, JacobiError, check  # noqa: F401
 from .solver import Jacobi, probe_copy, probe_update, tile_supported  # noqa: F401
 from .batch import JacobiBatch  # noqa: F401
-from .guess import GuessNet, param_count  # noqa: F401
+from .guess import GuessNet, init_params, param_count  # noqa: F401
 
 __all__ = ["Jacobi", "JacobiBatch", "GuessNet", "param_count", "JacobiError", "lib", "LIB_PATH", "probe_copy",
            "probe_update", "tile_supported"]

@@ -97,6 +97,8 @@ _SIGS = {
     "jacobi_batch_create": ([_bdescp, ctypes.POINTER(_h)], ctypes.c_int),
     "jacobi_batch_sweep": ([_h, ctypes.c_int64], ctypes.c_int),
     "jacobi_batch_residual": ([_h, _dp, _dp], ctypes.c_int),
+    "jacobi_batch_solve": ([_h, ctypes.c_double, _dp, ctypes.c_int64, ctypes.c_int64,
+                            _i64p, _dp], ctypes.c_int),
     "jacobi_batch_current": ([_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
                               _i64p], ctypes.c_int),
     "jacobi_batch_info": ([_h, _i64p, _i32p, _i32p, _i32p, _dp], ctypes.c_int),

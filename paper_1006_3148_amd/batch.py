@@ -81,6 +81,17 @@ class JacobiBatch:
         check(lib.jacobi_batch_residual(self._h, l2, mx))
         return np.array(l2[:]), np.array(mx[:])
 
+    def solve(self, rel_tol: float, max_sweeps: int, check_every: int, r0=None):
+        """Per-problem first sweep count at which ||r|| <= rel_tol * r0."""
+        ref = None
+        if r0 is not None:
+            ref = (ctypes.c_double * self.count)(*[float(x) for x in r0])
+        done = (ctypes.c_int64 * self.count)()
+        fin = (ctypes.c_double * self.count)()
+        check(lib.jacobi_batch_solve(self._h, rel_tol, ref, int(max_sweeps),
+                                     int(check_every), done, fin))
+        return np.array(done[:]), np.array(fin[:])
+
     def sync(self) -> None:
         check(lib.jacobi_batch_sync(self._h))
 

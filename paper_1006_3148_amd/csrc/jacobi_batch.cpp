@@ -541,6 +541,46 @@ int jacobi_batch_residual(jacobi_batch_t* h, double* l2, double* maxabs)
     return JACOBI_OK;
 }
 
+int jacobi_batch_solve(jacobi_batch_t* h, double rel_tol, const double* r0,
+                       int64_t max_sweeps, int64_t check_every, int64_t* sweeps_done,
+                       double* final_l2)
+{
+    if (!h || !sweeps_done || !final_l2) return fail(JACOBI_EINVAL, "null argument");
+    if (!(rel_tol > 0) || max_sweeps < 0 || check_every < 1)
+        return fail(JACOBI_EINVAL, "need rel_tol > 0, max_sweeps >= 0, check_every >= 1");
+    std::vector<double> r(h->count), ref(h->count);
+    std::vector<char> done(h->count, 0);
+    int rc = jacobi_batch_residual(h, r.data(), nullptr);
+    if (rc != JACOBI_OK) return rc;
+    for (int q = 0; q < h->count; ++q) {
+        ref[q] = (r0 && r0[q] > 0) ? r0[q] : r[q];
+        sweeps_done[q] = -1;
+        final_l2[q] = r[q];
+    }
+    int64_t swept = 0;
+    int left = h->count;
+    for (;;) {
+        for (int q = 0; q < h->count; ++q) {
+            if (!done[q] && r[q] <= rel_tol * ref[q]) {
+                done[q] = 1;
+                --left;
+                sweeps_done[q] = swept;
+                final_l2[q] = r[q];
+            }
+        }
+        if (left == 0 || swept >= max_sweeps) break;
+        const int64_t m = std::min(check_every, max_sweeps - swept);
+        rc = jacobi_batch_sweep(h, m);
+        if (rc != JACOBI_OK) return rc;
+        swept += m;
+        rc = jacobi_batch_residual(h, r.data(), nullptr);
+        if (rc != JACOBI_OK) return rc;
+    }
+    for (int q = 0; q < h->count; ++q)
+        if (!done[q]) final_l2[q] = r[q];
+    return JACOBI_OK;
+}
+
 int jacobi_batch_current(jacobi_batch_t* h, int32_t i, void** origin,
                          int64_t strides[3])
 {

@@ -40,6 +40,21 @@ def param_count(levels: int) -> int:
     return c.value
 
 
+def init_params(levels: int, seed: int) -> np.ndarray:
+    """Initial parameters: He-normal conv weights (std sqrt(2/(27*16))), zero
+    biases, head weights N(0, 1/16), zero head bias; numpy PCG64(seed), drawn
+    layer by layer in parameter order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    layers = (param_count(levels) - 17) // (27 * 256 + 16)
+    parts = []
+    for _ in range(layers):
+        parts.append(rng.standard_normal(27 * 256) * np.sqrt(2.0 / (27 * 16)))
+        parts.append(np.zeros(16))
+    parts.append(rng.standard_normal(16) * np.sqrt(1.0 / 16))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts)
+
+
 class GuessNet:
     """The U-Net on the GPU.  ``params`` (numpy FP32/FP64 vector) initialises
     the FP32 master parameters; gradients and Adam moments are allocated

@@ -21,6 +21,8 @@ from .grids import (  # noqa: F401
     uniform_box,
     sine_face_box,
     sine_face_modes,
+    sine_faces,
+    unit_face_mode_box,
     batch_dims,
     batch_problems,
     zero_edges,

@@ -142,3 +142,36 @@ def batch_problems(count: int, seed: int, lo: int = 32, step: int = 16,
             yield nx, ny, nz, box
         else:
             yield nx, ny, nz, None
+
+
+def sine_faces(n: int, seed: int, modes_per_face: int = 8, pmax: int = 4):
+    """The six face arrays of ``sine_face_box(n, n, n, seed)`` (cubic grids).
+
+    Returns an array of shape (6, n+2, n+2): face f in ``FACES`` order, indexed
+    [b, a] with (a, b) the face's in-plane axes in (i, j, k) order.  Values
+    on the box edges are left as computed (the stencil never reads them).
+    """
+    modes = sine_face_modes(seed, modes_per_face, pmax)
+    return np.stack([_face_values(m, n, n) for m in modes]), modes
+
+
+def unit_face_mode_box(n: int, face: int, p: int, q: int) -> np.ndarray:
+    """Cubic box whose face ``face`` (``FACES`` order) carries the single mode
+    sin(pi p a/(n+1)) sin(pi q b/(n+1)); other faces, interior and edges 0."""
+    g = _face_values([(p, q, 1.0)], n, n)
+    box = np.zeros((n + 2, n + 2, n + 2), dtype=np.float64)
+    if face == 0:
+        box[:, :, 0] = g
+    elif face == 1:
+        box[:, :, -1] = g
+    elif face == 2:
+        box[:, 0, :] = g
+    elif face == 3:
+        box[:, -1, :] = g
+    elif face == 4:
+        box[0, :, :] = g
+    else:
+        box[-1, :, :] = g
+    box[1:-1, 1:-1, 1:-1] = 0.0
+    zero_edges(box)
+    return box
