@@ -6,7 +6,12 @@ the Jacobi method of Sect. 1.1.  Architecture (the reading this build takes):
 * input lift: for interior cell (i,j,k) of an N^3 grid, 16 channels =
   the six face values at its projections onto the boundary faces
   (i=0, i=N+1, j=0, j=N+1, k=0, k=N+1, in that order), the three
-  coordinates (i/(N+1) - 1/2, j/(N+1) - 1/2, k/(N+1) - 1/2), and 7 zeros;
+  coordinates (i/(N+1) - 1/2, j/(N+1) - 1/2, k/(N+1) - 1/2), the face blend
+  b (below), and 6 zeros;
+* face blend b(i,j,k) = sum_f g_f w_f / sum_f w_f over the six face values
+  g_f at the cell's projections with w_f = 1 / (distance to face f), i.e.
+  1/i, 1/(N+1-i), 1/j, ...; the network predicts a correction to it:
+  out = b + head(...);
 * U-Net with L levels (N, N/2, ..., N/2^(L-1)) and C = 16 channels:
   encoder level l: h = relu(conv(x)); h = relu(conv(h)); skip_l = h;
   if l < L-1: x = relu(conv_stride2(h));
@@ -16,6 +21,11 @@ the Jacobi method of Sect. 1.1.  Architecture (the reading this build takes):
 * every conv is 3x3x3, zero padding 1, stride 1 (or 2 for the down convs),
   with a per-output-channel bias; up2 is nearest-neighbour upsampling by 2;
 * loss = mean over the interior of (out - target)^2.
+
+The blend term (not in the first version of this network) was added because
+a plain U-Net trained for two epochs left a smooth interior error that the
+Jacobi sweeps remove slowest; predicting the correction to the blend keeps
+the blend's low-frequency accuracy.
 
 Layout: activations (D, H, W, C) with the channel index last; conv weights
 (27, Cout, Cin) with tap index t = (dz+1)*9 + (dy+1)*3 + (dx+1).
@@ -62,7 +72,28 @@ def lift(box):
     x[..., 6] = i[None, None, :]
     x[..., 7] = j[None, :, None]
     x[..., 8] = k[:, None, None]
+    x[..., 9] = blend(box)
     return x
+
+
+def blend(box):
+    """Inverse-distance blend of the six face values at each cell's projections."""
+    nz2, ny2, nx2 = box.shape
+    nz, ny, nx = nz2 - 2, ny2 - 2, nx2 - 2
+    ci = np.arange(1, nx + 1, dtype=np.float64)[None, None, :]
+    cj = np.arange(1, ny + 1, dtype=np.float64)[None, :, None]
+    ck = np.arange(1, nz + 1, dtype=np.float64)[:, None, None]
+    terms = [
+        (box[1:-1, 1:-1, 0][:, :, None], 1.0 / ci),
+        (box[1:-1, 1:-1, -1][:, :, None], 1.0 / (nx + 1 - ci)),
+        (box[1:-1, 0, 1:-1][:, None, :], 1.0 / cj),
+        (box[1:-1, -1, 1:-1][:, None, :], 1.0 / (ny + 1 - cj)),
+        (box[0, 1:-1, 1:-1][None, :, :], 1.0 / ck),
+        (box[-1, 1:-1, 1:-1][None, :, :], 1.0 / (nz + 1 - ck)),
+    ]
+    num = sum(g * w for g, w in terms)
+    den = sum(np.broadcast_to(w, num.shape) for _, w in terms)
+    return num / den
 
 
 def taps():
@@ -187,7 +218,7 @@ def forward(theta, box, levels, round_bf16=True):
         h2 = rnd(relu(conv3(h, w["dec%d_b.w" % l], w["dec%d_b.b" % l])))
         cache["dec%d_b" % l] = (h, h2)
         x = h2
-    out = x @ p["head.w"] + p["head.b"][0]
+    out = x @ p["head.w"] + p["head.b"][0] + blend(box)
     cache["last"] = x
     return out, (cache, w, p)
 

@@ -64,7 +64,17 @@ def test_lift_channels():
     assert x[k, j, i, 4] == box[0, j + 1, i + 1]
     assert x[k, j, i, 5] == box[-1, j + 1, i + 1]
     assert np.isclose(x[k, j, i, 6], (i + 1) / 6 - 0.5)
-    assert np.all(x[..., 9:] == 0)
+    assert np.all(x[..., 10:] == 0)
+    # blend: a box whose six faces are constant c gives c everywhere
+    cbox = np.full((6, 5, 7), 2.5)
+    assert np.allclose(cv.lift(cbox)[..., 9], 2.5)
+    # and a face only on i=0 weighs by 1/i against the 6 inverse distances
+    fbox = np.zeros((6, 5, 7))
+    fbox[1:-1, 1:-1, 0] = 1.0
+    b = cv.blend(fbox)
+    i, j, kk = 2, 1, 3
+    ws = [1 / (i + 1), 1 / (6 - (i + 1)), 1 / (j + 1), 1 / (4 - (j + 1)), 1 / (kk + 1), 1 / (5 - (kk + 1))]
+    assert np.isclose(b[kk, j, i], ws[0] / sum(ws))
 
 
 def test_bf16_round_matches_torch():
