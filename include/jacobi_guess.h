@@ -8,11 +8,13 @@
  * the solver.  The network is a small 3D U-Net:
  *   - input: 16 channels per interior cell = the six face values at the
  *     cell's projections (faces i=0, i=n+1, j=0, j=n+1, k=0, k=n+1), the
- *     three centred coordinates x/(n+1) - 1/2, and 7 zeros;
+ *     three centred coordinates x/(n+1) - 1/2, the face blend b, 6 zeros;
+ *     b = sum_f g_f w_f / sum_f w_f with w_f = 1/(distance to face f);
  *   - `levels` resolutions n, n/2, ...; per encoder level two 3x3x3 conv +
  *     ReLU, then a stride-2 3x3x3 conv + ReLU down; per decoder level a
  *     nearest x2 upsampling added to the encoder output of that level, then
- *     two 3x3x3 conv + ReLU; a 1x1x1 head to one output channel;
+ *     two 3x3x3 conv + ReLU; a 1x1x1 head to one output channel, added to
+ *     b (the network predicts a correction to the blend);
  *   - 16 channels everywhere, zero padding, BF16 weights and activations,
  *     FP32 accumulation (MFMA), FP32 master parameters and gradients.
  * Flat FP32 parameter vector, in this order: for every conv layer (enc0_a,

@@ -21,8 +21,8 @@ namespace {
 struct Layout {
     size_t total = 0;
     // byte offsets
-    size_t w = 0, wt = 0, woff = 0, in = 0, out = 0, loss = 0, lpart = 0, gpart = 0,
-           wpart = 0;
+    size_t w = 0, wt = 0, woff = 0, in = 0, out = 0, blend = 0, loss = 0, lpart = 0,
+           gpart = 0, wpart = 0;
     std::vector<size_t> ea, eb, dn, sm, da, db, ga, gb, gs;
 };
 
@@ -47,6 +47,7 @@ bool plan(int64_t n, int L, Layout* lay)
     auto vox = [&](int lev) { const int64_t d = n >> lev; return (size_t)(d * d * d); };
     l.in = add(off, vox(0) * kC * 2);
     l.out = add(off, vox(0) * 4);
+    l.blend = add(off, vox(0) * 4);
     l.loss = add(off, 8);
     l.lpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 8);
     l.gpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 17 * 4);
@@ -196,7 +197,7 @@ int jg_forward(jg_net* h, const double* box, float* out)
     const int L = h->L;
     hipError_t e = prep_weights(h->params, at<int64_t>(h, l.woff), h->nl,
                                 at<uint16_t>(h, l.w), at<uint16_t>(h, l.wt), h->s);
-    if (e == hipSuccess) e = lift(box, (int)h->n, A(h, l.in), h->s);
+    if (e == hipSuccess) e = lift(box, (int)h->n, A(h, l.in), F(h, l.blend), h->s);
     const uint16_t* x = A(h, l.in);
     for (int lev = 0; lev < L && e == hipSuccess; ++lev) {
         const int d = (int)(h->n >> lev);
@@ -226,8 +227,8 @@ int jg_forward(jg_net* h, const double* box, float* out)
     const float* hw = h->params + (size_t)h->nl * kConvP;
     const int64_t nv = h->n * h->n * h->n;
     if (e == hipSuccess)
-        e = head(x, nv, hw, hw + kC, F(h, l.out), nullptr, nullptr, nullptr, nullptr, nullptr,
-                 nullptr, nullptr, h->s);
+        e = head(x, nv, hw, hw + kC, F(h, l.blend), F(h, l.out), nullptr, nullptr, nullptr,
+                 nullptr, nullptr, nullptr, nullptr, h->s);
     if (e == hipSuccess && out)
         e = hipMemcpyAsync(out, F(h, l.out), nv * sizeof(float), hipMemcpyDeviceToDevice, h->s);
     if (e != hipSuccess) return hip_fail(e, "network forward");
@@ -247,7 +248,8 @@ int jg_backward(jg_net* h, const float* target, double* loss)
     float* wpart = F(h, l.wpart);
     const uint16_t* last = A(h, l.db[0]);
     // head: dx into ga[0] (masked by the last ReLU output), head gradients
-    hipError_t e = head(last, nv, hw, hw + kC, F(h, l.out), target, F(h, l.ga[0]),
+    hipError_t e = head(last, nv, hw, hw + kC, F(h, l.blend), F(h, l.out), target,
+                        F(h, l.ga[0]),
                         at<double>(h, l.lpart), F(h, l.gpart), at<double>(h, l.loss),
                         gparam_head, gparam_head + kC, h->s);
     // decoder, from level 0 up: ga[lev] holds the gradient of dec_b's output

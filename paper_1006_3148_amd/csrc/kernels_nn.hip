@@ -67,9 +67,12 @@ __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c)
 
 // ---------------------------------------------------------------- lift ----
 // x[k][j][i][c] for the interior of an (n+2)^3 FP64 box: six face values,
-// three centred coordinates, zeros.
+// three centred coordinates, the inverse-distance blend of the six face
+// values (also written to blend[v] in FP32: the network output is blend +
+// head), zeros.
 __global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ box,
-                                                   int n, uint16_t* __restrict__ x)
+                                                   int n, uint16_t* __restrict__ x,
+                                                   float* __restrict__ blend)
 {
     const int64_t nv = (int64_t)n * n * n;
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -77,25 +80,39 @@ __global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ bo
     const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / ((int64_t)n * n));
     const int64_t p = n + 2, pp = p * p;
     const int64_t kk = k + 1, jj = j + 1, ii = i + 1;
+    double g[6];
+    g[0] = box[kk * pp + jj * p + 0];
+    g[1] = box[kk * pp + jj * p + (n + 1)];
+    g[2] = box[kk * pp + 0 * p + ii];
+    g[3] = box[kk * pp + (int64_t)(n + 1) * p + ii];
+    g[4] = box[0 * pp + jj * p + ii];
+    g[5] = box[(int64_t)(n + 1) * pp + jj * p + ii];
+    const double w[6] = {1.0 / (i + 1), 1.0 / (n - i), 1.0 / (j + 1),
+                         1.0 / (n - j), 1.0 / (k + 1), 1.0 / (n - k)};
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        num = num + g[f] * w[f];
+        den = den + w[f];
+    }
+    const double b = num / den;
     float c[16];
-    c[0] = (float)box[kk * pp + jj * p + 0];
-    c[1] = (float)box[kk * pp + jj * p + (n + 1)];
-    c[2] = (float)box[kk * pp + 0 * p + ii];
-    c[3] = (float)box[kk * pp + (int64_t)(n + 1) * p + ii];
-    c[4] = (float)box[0 * pp + jj * p + ii];
-    c[5] = (float)box[(int64_t)(n + 1) * pp + jj * p + ii];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) c[f] = (float)g[f];
     c[6] = (float)((double)(i + 1) / (n + 1) - 0.5);
     c[7] = (float)((double)(j + 1) / (n + 1) - 0.5);
     c[8] = (float)((double)(k + 1) / (n + 1) - 0.5);
+    c[9] = (float)b;
 #pragma unroll
-    for (int q = 9; q < 16; ++q) c[q] = 0.f;
-    uint32_t w[8];
+    for (int q = 10; q < 16; ++q) c[q] = 0.f;
+    blend[v] = (float)b;
+    uint32_t wd[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-        w[q] = (uint32_t)f2bf(c[2 * q]) | ((uint32_t)f2bf(c[2 * q + 1]) << 16);
+        wd[q] = (uint32_t)f2bf(c[2 * q]) | ((uint32_t)f2bf(c[2 * q + 1]) << 16);
     uint4* dst = reinterpret_cast<uint4*>(x + v * 16);
-    dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-    dst[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    dst[0] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    dst[1] = make_uint4(wd[4], wd[5], wd[6], wd[7]);
 }
 
 // ------------------------------------------------------ conv forward ----
@@ -312,15 +329,16 @@ __global__ __launch_bounds__(256) void up_bwd_kernel(const float* __restrict__ d
 }
 
 // ------------------------------------------------------------- head ----
-// out = hw . x + hb (FP32).  With a target: per-block partial sums of
+// out = blend + hw . x + hb (FP32).  With a target: per-block partial sums of
 // (out - target)^2 and dout = 2 (out - target) / nvox written to dx as
 // dx[v][c] = dout * hw[c] (masked by x > 0), and per-block partials of
 // dhw[c] = sum dout x[c], dhb = sum dout.
 __global__ __launch_bounds__(256) void head_kernel(
     const uint16_t* __restrict__ x, int64_t nvox, const float* __restrict__ hw,
-    const float* __restrict__ hb, float* __restrict__ out,
-    const float* __restrict__ target, float* __restrict__ dx,
-    double* __restrict__ loss_part, float* __restrict__ gpart)
+    const float* __restrict__ hb, const float* __restrict__ blend,
+    float* __restrict__ out, const float* __restrict__ target,
+    float* __restrict__ dx, double* __restrict__ loss_part,
+    float* __restrict__ gpart)
 {
     __shared__ double sl[256];
     __shared__ float sg[17][256];
@@ -339,6 +357,7 @@ __global__ __launch_bounds__(256) void head_kernel(
         o = hb[0];
 #pragma unroll
         for (int c = 0; c < 16; ++c) o += hw[c] * xc[c];
+        o += blend[v];
         if (out) out[v] = o;
     } else {
 #pragma unroll
@@ -462,10 +481,11 @@ int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 }  // namespace
 
-hipError_t lift(const double* box, int n, uint16_t* x, hipStream_t s)
+hipError_t lift(const double* box, int n, uint16_t* x, float* blend, hipStream_t s)
 {
     const int64_t nv = (int64_t)n * n * n;
-    hipLaunchKernelGGL(lift_kernel, dim3(blocks_for(nv, 256)), dim3(256), 0, s, box, n, x);
+    hipLaunchKernelGGL(lift_kernel, dim3(blocks_for(nv, 256)), dim3(256), 0, s, box, n, x,
+                       blend);
     return hipGetLastError();
 }
 
@@ -548,12 +568,13 @@ hipError_t up_bwd(const float* ds, float* dx, int d, const uint16_t* mask, hipSt
 int head_blocks(int64_t nvox) { return blocks_for(nvox, 256); }
 
 hipError_t head(const uint16_t* x, int64_t nvox, const float* hw, const float* hb,
-                float* out, const float* target, float* dx, double* loss_part,
-                float* gpart, double* loss, float* ghw, float* ghb, hipStream_t s)
+                const float* blend, float* out, const float* target, float* dx,
+                double* loss_part, float* gpart, double* loss, float* ghw, float* ghb,
+                hipStream_t s)
 {
     const int blocks = head_blocks(nvox);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks), dim3(256), 0, s, x, nvox, hw, hb, out,
-                       target, dx, loss_part, gpart);
+    hipLaunchKernelGGL(head_kernel, dim3(blocks), dim3(256), 0, s, x, nvox, hw, hb, blend,
+                       out, target, dx, loss_part, gpart);
     if (target) {
         hipLaunchKernelGGL(sum_loss_kernel, dim3(1), dim3(256), 0, s, loss_part, blocks, nvox,
                            loss);

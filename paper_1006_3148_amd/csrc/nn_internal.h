@@ -11,7 +11,7 @@ constexpr int kC = 16;                      // channels
 constexpr int64_t kConvW = 27 * kC * kC;    // weights per conv layer
 constexpr int64_t kConvP = kConvW + kC;     // weights + bias per conv layer
 
-hipError_t lift(const double* box, int n, uint16_t* x, hipStream_t s);
+hipError_t lift(const double* box, int n, uint16_t* x, float* blend, hipStream_t s);
 hipError_t conv_fwd(const uint16_t* x, int din, const uint16_t* w, const float* b,
                     uint16_t* y, int stride, bool relu, hipStream_t s);
 hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* wt, float* dx,
@@ -26,8 +26,9 @@ hipError_t up_bwd(const float* ds, float* dx, int d, const uint16_t* mask,
                   hipStream_t s);
 int head_blocks(int64_t nvox);
 hipError_t head(const uint16_t* x, int64_t nvox, const float* hw, const float* hb,
-                float* out, const float* target, float* dx, double* loss_part,
-                float* gpart, double* loss, float* ghw, float* ghb, hipStream_t s);
+                const float* blend, float* out, const float* target, float* dx,
+                double* loss_part, float* gpart, double* loss, float* ghw, float* ghb,
+                hipStream_t s);
 hipError_t write_guess(const float* out, int n, double* box, hipStream_t s);
 hipError_t prep_weights(const float* params, const int64_t* woff, int layers,
                         uint16_t* w, uint16_t* wt, hipStream_t s);
