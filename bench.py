@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the batched / 1024^3 / time-to-tolerance extras")
     ap.add_argument("--probe", action="store_true",
                     help="only run the copy probe (1 GiB in, 1 GiB out) 5 times; "
                          "used to scale HBM byte counters")
@@ -237,11 +239,93 @@ def main():
                 w, _, tm, _ = run_config(n, sweeps, tt, lay, 1, 1, torch, box)
                 tab["%s_t%d" % (lay, tt)] = round(glups(n, sweeps, w), 1)
         extra["glups_by_layout_t_512"] = tab
+        if not args.quick:
+            extra["n1024_compressed"] = bench_1024(torch, t)
+            extra["batched_256"] = bench_batched(torch)
+            extra["time_to_1e-8_256"] = bench_time_to_tol(torch, 256, t)
         out["extra"] = extra
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_1024(torch, t, sweeps=48):
+    """Compressed single grid at 1024^3 (8.6 GB + shift planes): GLUP/s."""
+    import synth
+    from paper_1006_3148_amd import Jacobi
+    box = synth.sine_face_box(1024, 1024, 1024, seed=3)
+    j = Jacobi(box, t=t, layout="compressed")
+    del box
+    j.sweep(2 * t)
+    j.sync()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    j.sweep(sweeps)
+    j.sync()
+    dt = time.perf_counter() - a
+    info = j.info()
+    j.close()
+    torch.cuda.empty_cache()
+    return {"sweeps": sweeps, "t": t, "seg_len": info["seg_len"],
+            "glups": round(1024 ** 3 * sweeps / dt / 1e9, 1),
+            "roofline_frac_spec": round(1024 ** 3 * sweeps / dt / 1e9 / (HBM_PEAK_GBS * t / 16.0), 4)}
+
+
+def bench_batched(torch, count=256, seed=4, sweeps=500):
+    """256 uneven problems (edges 32..192 step 16), 500 sweeps, autotuned
+    tile shape and t, hipGraph replay; FP64 and FP32-refined."""
+    import synth
+    from paper_1006_3148_amd import JacobiBatch
+    probs = list(synth.batch_problems(count, seed))
+    boxes = [p[3] for p in probs]
+    cells = float(sum(p[0] * p[1] * p[2] for p in probs))
+    res = {"problems": count, "cells": cells, "sweeps": sweeps}
+    for dtype in ("f64", "f32_refined"):
+        b = JacobiBatch(boxes, t=0, dtype=dtype, inner_sweeps=50)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        b.sweep(sweeps)          # autotune + capture + replay
+        b.sync()
+        first = time.perf_counter() - a
+        a = time.perf_counter()
+        b.sweep(sweeps)          # graph replay of the same schedule
+        b.sync()
+        steady = time.perf_counter() - a
+        info = b.info()
+        res[dtype] = {"first_call_s": round(first, 4), "steady_s": round(steady, 4),
+                      "glups": round(cells * sweeps / steady / 1e9, 1),
+                      "t": info["t"], "tile_rows": info["tile_rows"],
+                      "tune_ms": round(info["tune_ms"], 2),
+                      "tune_log": [(e["t"], e["tile_rows"], round(e["glups"], 1))
+                                   for e in b.tune_log()]}
+        b.close()
+    del boxes
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024):
+    """Sweeps and seconds to ||r|| <= 1e-8 ||r0|| from the zero start with
+    sine-mode faces: FP64 blocked (t), FP32-refined, plain FP64 t=1."""
+    import synth
+    from paper_1006_3148_amd import Jacobi
+    box = synth.sine_face_box(n, n, n, seed=3)
+    res = {"n": n, "rel_tol": rel_tol, "check_every": check}
+    for name, kw in (("f64_blocked", dict(t=t)),
+                     ("f32_refined", dict(t=t, dtype="f32_refined", inner_sweeps=check)),
+                     ("f64_single_sweep", dict(t=1))):
+        j = Jacobi(box, **kw)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        done, fin = j.solve(rel_tol, 5_000_000, check)
+        dt = time.perf_counter() - a
+        r0 = None
+        j.close()
+        res[name] = {"sweeps": done, "seconds": round(dt, 3), "final_l2": fin,
+                     "glups": round(n ** 3 * done / dt / 1e9, 1)}
+    torch.cuda.empty_cache()
+    return res
 
 
 def _kernel_hash():
