@@ -1,0 +1,93 @@
+// Device helpers shared by the trip kernels (kernels_trip.hip and
+// kernels_pipe.hip).  Included inside an anonymous namespace of each
+// translation unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace jacobi_impl {
+namespace {
+
+template <typename Real>
+struct Sixth;
+template <>
+struct Sixth<double> {
+    static constexpr double v = 1.0 / 6.0;
+};
+template <>
+struct Sixth<float> {
+    static constexpr float v = 1.0f / 6.0f;
+};
+
+// DPP wave shifts (GFX9 family): wave_shr:1 gives lane L the value of lane
+// L-1, wave_shl:1 the value of lane L+1.  Lanes without a source read 0
+// (bound_ctrl).
+__device__ __forceinline__ int lane_from_left(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ int lane_from_right(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
+}
+__device__ __forceinline__ float from_left(float v)
+{
+    return __int_as_float(lane_from_left(__float_as_int(v)));
+}
+__device__ __forceinline__ float from_right(float v)
+{
+    return __int_as_float(lane_from_right(__float_as_int(v)));
+}
+__device__ __forceinline__ double from_left(double v)
+{
+    int lo = lane_from_left(__double2loint(v));
+    int hi = lane_from_left(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_right(double v)
+{
+    int lo = lane_from_right(__double2loint(v));
+    int hi = lane_from_right(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Workgroup b is dispatched to XCD b % 8.  Give each XCD a contiguous range
+// of the tile order so that tiles sharing ghost cells share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles)
+{
+    const int x = b & 7, idx = b >> 3;
+    const int q = ntiles >> 3, r = ntiles & 7;
+    return x * q + min(x, r) + idx;
+}
+
+__device__ __forceinline__ int flag_load(const int* f)
+{
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_store(int* f, int v)
+{
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kDone = 0x7fffffff;
+
+// Planes in flight per tile (register ring depth).
+#ifndef JACOBI_PREFETCH
+#define JACOBI_PREFETCH 3
+#endif
+constexpr int kPrefetch = JACOBI_PREFETCH;
+
+// Geometry and pointers of the problem a tile belongs to.
+struct Geo {
+    const void* src;
+    void* dst;
+    const float* rhs;
+    int64_t px, py, rpx, rpy;
+    int nx, ny, nz;
+    int tiles_x, tiles_y, segs, seg_len;
+};
+
+}  // namespace
+}  // namespace jacobi_impl
