@@ -17,7 +17,11 @@
 //    order of Eq. (1) exactly: i-1, i+1, j-1, j+1, k-1, k+1;
 //  * i-neighbours come from the adjacent lanes through DPP wave shifts, j
 //    neighbours from the wave's own registers, and the two edge rows of each
-//    wave through LDS (one barrier per stage, double-buffered);
+//    wave through LDS;
+//  * stage s consumes in step n what stage s-1 produced in step n-1 (stage s
+//    runs two planes behind stage s-1 instead of one).  The edge rows of all
+//    T stages are then exchanged together, with one barrier per step, and
+//    the T stages of a step are independent chains of arithmetic;
 //  * tiles overlap by T cells in i and j and by T planes between k segments
 //    (ghost zones): stage s is exact on a region that shrinks by one cell per
 //    stage, and only the central (64-2T) x (R*W-2T) x seg_len block is stored.
@@ -39,6 +43,7 @@
 // bitwise equal to the plain definition.
 
 #include <type_traits>
+#include <utility>
 
 #include "internal.h"
 #include "trip_device.h"
@@ -46,13 +51,38 @@
 namespace jacobi_impl {
 namespace {
 
+template <int... Is, typename F>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, Is...>, F&& f)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    static_for_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// Edge-row exchange buffers in LDS: [buffer][stage][wave][top/bottom][lane].
+// Two buffers (one barrier per step) when they fit comfortably, else one
+// buffer and a second barrier per step before it is rewritten.
+template <typename Real, int T, int W>
+struct Xch {
+    static constexpr size_t one = (size_t)T * W * 2 * 64 * sizeof(Real);
+    static constexpr int nbuf = 2 * one <= 96 * 1024 ? 2 : 1;
+};
+
 template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE>
 __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int tile,
-                                         Real (*xch)[W][2][64])
+                                         Real (*xch)[T][W][2][64])
 {
     constexpr int H = R * W;
     constexpr int OX = 64 - 2 * T;
     constexpr int OY = H - 2 * T;
+    constexpr int NB = Xch<Real, T, W>::nbuf;
+    constexpr int NR = RHS ? 2 * T - 1 : 1;  // rhs planes held per row
+    // Steps per unrolled chunk: PF, so that the prefetch slot of every step
+    // is a compile-time constant (no register copies of loads in flight).
+    constexpr int U = PF;
     const Real c6 = Sixth<Real>::v;
 
     const int lane = threadIdx.x & 63;
@@ -69,7 +99,9 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     const int k1 = min(k0 + g.seg_len, g.nz + 2);
     const int a = max(k0 - T, 0);
     const int b = min(k1 - 1 + T, g.nz + 1);
-    const int nsteps = k1 - a + T;
+    // Stage s (1-based) completes plane a+n-2s+1 in step n; the last output
+    // plane k1-1 of stage T is completed in step k1-a+2T-2.
+    const int nsteps = k1 - a + 2 * T - 1;
 
     const Real* __restrict__ src = static_cast<const Real*>(g.src);
     Real* __restrict__ dst = static_cast<Real*>(g.dst);
@@ -115,196 +147,197 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     }
     int known = FLAGS ? 0 : kDone;
 
-    Real P[T][R], C[T][R];
+    // X[s]: the plane stage s+1 consumes in this step (a plane of stage s,
+    // produced by stage s in the previous step); X[T]: the plane stage T
+    // completed.  P, C: per-stage k-streaming state (partial sum, and the
+    // plane consumed in the previous step).
+    Real X[T + 1][R], P[T][R], C[T][R];
 #pragma unroll
-    for (int s = 0; s < T; ++s)
+    for (int r = 0; r < R; ++r) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int s = 0; s <= T; ++s) X[s][r] = Real(0);
+#pragma unroll
+        for (int s = 0; s < T; ++s) {
             P[s][r] = Real(0);
             C[s][r] = Real(0);
         }
-    float rq[RHS ? T : 1][R];
+    }
+    // rr[m]: rhs plane a+n-1-m; stage s+1 completes plane a+n-2s-1 and takes
+    // rr[2s].
+    float rr[NR][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int m = 0; m < NR; ++m)
 #pragma unroll
-        for (int s = 0; s < (RHS ? T : 1); ++s) rq[s][r] = 0.f;
+        for (int r = 0; r < R; ++r) rr[m][r] = 0.f;
 
-    // Addressing: a scalar (per-plane) base plus a 32-bit per-row byte offset
-    // that is loop invariant; src, dst and rhs frames share the pitches.
-    uint32_t voff[R];
+    // Addressing: a per-plane buffer descriptor (scalar) plus a 32-bit
+    // per-row byte offset that is loop invariant; src, dst and rhs frames
+    // share the pitches.  Cells outside the box (edge tiles) load as 0 and
+    // cells this tile does not own are not stored, through out-of-range
+    // offsets.
+    uint32_t voff[R], soff[R], roff[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        voff[r] = (uint32_t)(((int64_t)(j0 + r) * px + i) * (int64_t)sizeof(Real));
+    for (int r = 0; r < R; ++r) {
+        const uint32_t o =
+            (uint32_t)(((int64_t)(j0 + r) * px + i) * (int64_t)sizeof(Real));
+        voff[r] = (!EDGE || (lane_box && row_box[r])) ? o : kOob;
+        soff[r] = (lane_out && row_out[r]) ? o : kOob;
+        roff[r] = RHS ? voff[r] / (uint32_t)(sizeof(Real) / sizeof(float)) : 0u;
+    }
     const int64_t plane_bytes = py * (int64_t)sizeof(Real);
+    const uint32_t plane_b32 = (uint32_t)plane_bytes;
     const char* src_b = reinterpret_cast<const char*>(src);
     const char* rhs_b = reinterpret_cast<const char*>(g.rhs);
     char* dst_b = reinterpret_cast<char*>(dst);
     const int64_t rplane_bytes = g.rpy * (int64_t)sizeof(float);
 
-    // Register ring of the next PF input planes (and rhs planes): plane
-    // loads are issued PF steps before use, so each step does not wait for a
-    // full memory round trip.
+    // Register ring of the next PF input planes (and rhs planes): slot
+    // n % PF holds plane a+n; its load is issued PF steps before use, so a
+    // step does not wait for a full memory round trip.  Planes past b load
+    // as 0.
     Real ring[PF][R];
     float rring[RHS ? PF : 1][R];
+    auto load_plane = [&](const int q, Real(&dstv)[R]) {
+        const Rsrc rs = make_rsrc(src_b + (int64_t)min(q, b) * plane_bytes,
+                                  q <= b ? plane_b32 : 0u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) dstv[r] = buf_load<Real>(rs, voff[r]);
+    };
+    auto load_rhs = [&](const int qr, float(&dstv)[R]) {
+        const bool in = qr >= 1 && qr <= g.nz;
+        const Rsrc rs = make_rsrc(rhs_b + (int64_t)(in ? qr : 1) * rplane_bytes,
+                                  in ? (uint32_t)rplane_bytes : 0u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) dstv[r] = buf_load<float>(rs, roff[r]);
+    };
 #pragma unroll
     for (int d = 0; d < PF; ++d) {
-        const int q = a + d;
-        const char* sp = src_b + (int64_t)q * plane_bytes;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            ring[d][r] = Real(0);
-            if (q <= b && (!EDGE || (lane_box && row_box[r])))
-                ring[d][r] = *reinterpret_cast<const Real*>(sp + voff[r]);
-        }
-        if (RHS) {
-            const int qr = a - 1 + d;  // rhs plane stage 1 uses at step d
-            const char* rp = rhs_b + (int64_t)qr * rplane_bytes;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                rring[RHS ? d : 0][r] = 0.f;
-                if (qr >= 1 && qr <= g.nz && (!EDGE || (lane_box && row_box[r])))
-                    rring[RHS ? d : 0][r] = *reinterpret_cast<const float*>(
-                        rp + voff[r] / (sizeof(Real) / sizeof(float)));
-            }
-        }
+        load_plane(a + d, ring[d]);
+        if (RHS) load_rhs(a - 1 + d, rring[RHS ? d : 0]);  // stage 1, step d
     }
 
-    int phase = 0;
-#pragma unroll 2
-    for (int n = 0; n < nsteps; ++n) {
-        Real x[R];
+    // Store plane pe of the last stage (held in X[T]).  Called at the start
+    // of the next step, so that a step's stage arithmetic is not split by the
+    // conditional store.
+    auto store_out = [&](const int pe) {
+        const bool in = pe >= k0 && pe < k1;
+        if (FLAGS && in) {
+            // Storage plane overwritten by this store, in input-frame terms;
+            // planes outside the box are shift room nobody reads.
+            const int ow = p.dir > 0 ? pe - T : pe + T;
+            const int need = ow + 1;
+            if (ow >= 0 && ow <= g.nz + 1 && known < need) {
+                int64_t spins = 0;
+                for (;;) {
+                    int v = kDone;
+                    if (dep >= 0) v = flag_load(p.flags + (int64_t)dep * kFlagStride);
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = ring[0][r];
+                    for (int o = 1; o < 8; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
+                    v = __builtin_amdgcn_readfirstlane(v);
+                    if (v >= need) {
+                        known = v;
+                        break;
+                    }
+                    if (++spins > p.spin_limit || flag_load(p.err) != 0) {
+                        if (lane == 0) atomicCAS(p.err, 0, 1);
+                        known = kDone;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+        }
+        const Rsrc rd = make_rsrc(dst_b + (int64_t)(in ? pe : k0) * plane_bytes,
+                                  in ? plane_b32 : 0u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf_store(X[T][r], rd, soff[r]);
+    };
+
+    // One step: plane a+n enters stage 1, stage T completes plane a+n-2T+1.
+    // BND: some stage may complete the boundary plane 0 or nz+1
+    // (pass-through); only the first and last steps of a tile are such steps.
+    auto step = [&](const int n, auto slot_tag, auto bnd_tag) {
+        constexpr int sl = decltype(slot_tag)::value;
+        constexpr bool BND = decltype(bnd_tag)::value;
+        store_out(a + n - 2 * T);  // the plane the previous step completed
+#pragma unroll
+        for (int r = 0; r < R; ++r) X[0][r] = ring[sl][r];
         if (RHS) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) rq[0][r] = rring[0][r];
-        }
+            for (int m = NR - 1; m > 0; --m)
 #pragma unroll
-        for (int d = 0; d + 1 < PF; ++d)
+                for (int r = 0; r < R; ++r) rr[m][r] = rr[m - 1][r];
+#pragma unroll
+            for (int r = 0; r < R; ++r) rr[0][r] = rring[RHS ? sl : 0][r];
+        }
+        load_plane(a + n + PF, ring[sl]);
+        if (RHS) load_rhs(a + n + PF - 1, rring[RHS ? sl : 0]);
+
+        // One exchange of the edge rows of every stage's input per step: a
+        // stage consumes what the stage before it produced in the previous
+        // step, so the T stages of a step are independent of each other.
+        Real(*buf)[W][2][64] = xch[NB == 2 ? (n & 1) : 0];
+        if (NB == 1) __syncthreads();  // previous step's reads are done
+#pragma unroll
+        for (int s = 0; s < T; ++s) {
+            buf[s][wave][0][lane] = X[s][0];
+            buf[s][wave][1][lane] = X[s][R - 1];
+        }
+        __syncthreads();
+        if (FLAGS && threadIdx.x == 0) {
+            // every wave has finished step n-1: plane a+n-1 is consumed
+            flag_store(p.flags + (int64_t)tile * kFlagStride, a + n);
+        }
+
+        // Stage s+1 receives plane q = a+n-2s of stage s and completes plane
+        // q-1.  Descending s, so X[s+1] is overwritten after stage s+2 has
+        // read it.
+#pragma unroll
+        for (int s = T - 1; s >= 0; --s) {
+            const int pe = a + n - 2 * s - 1;
+            const Real up = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+            const Real dn = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+            const bool bnd = BND && ((pe == 0) || (pe == g.nz + 1));
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                ring[d][r] = ring[d + 1][r];
-                if (RHS) rring[RHS ? d : 0][r] = rring[RHS ? d + 1 : 0][r];
-            }
-        // Issue the loads of plane a+n+PF (used PF steps from now).
-        const int qn = a + n + PF;
-#pragma unroll
-        for (int r = 0; r < R; ++r) ring[PF - 1][r] = Real(0);
-        if (qn <= b) {
-            const char* sp = src_b + (int64_t)qn * plane_bytes;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (!EDGE || (lane_box && row_box[r]))
-                    ring[PF - 1][r] = *reinterpret_cast<const Real*>(sp + voff[r]);
-        }
-        if (RHS) {
-            const int qr = a + n + PF - 1;  // rhs plane stage 1 uses at step n+PF
-#pragma unroll
-            for (int r = 0; r < R; ++r) rring[RHS ? PF - 1 : 0][r] = 0.f;
-            if (qr >= 1 && qr <= g.nz) {
-                const char* rp = rhs_b + (int64_t)qr * rplane_bytes;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (!EDGE || (lane_box && row_box[r]))
-                        rring[RHS ? PF - 1 : 0][r] = *reinterpret_cast<const float*>(
-                            rp + voff[r] / (sizeof(Real) / sizeof(float)));
+                const Real xo = X[s][r];
+                const Real above = r == 0 ? up : X[s][r > 0 ? r - 1 : 0];
+                const Real below = r == R - 1 ? dn : X[s][r < R - 1 ? r + 1 : 0];
+                const Real inpl = ((from_left(xo) + from_right(xo)) + above) + below;
+                Real e;
+                if (bnd) {
+                    e = C[s][r];
+                } else {
+                    Real sum = P[s][r] + xo;
+                    if (RHS) sum = sum + (Real)rr[RHS ? 2 * s : 0][r];
+                    e = sum * c6;
+                    if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
+                }
+                P[s][r] = inpl + C[s][r];
+                C[s][r] = xo;
+                X[s + 1][r] = e;
             }
         }
+    };
 
-        // The T stages of this step.  Only the first and last steps of a tile
-        // see the boundary planes 0 and nz+1 (pass-through); the common steps
-        // take the branch-free variant.
-        auto stages = [&](auto bnd_tag) {
-            constexpr bool BND = decltype(bnd_tag)::value;
-#pragma unroll
-            for (int s = 0; s < T; ++s) {
-                const int q = a + n - s;  // plane arriving at stage s+1
-                const int pe = q - 1;     // plane stage s+1 completes now
-                Real(*buf)[2][64] = xch[phase & 1];
-                ++phase;
-                buf[wave][0][lane] = x[0];
-                buf[wave][1][lane] = x[R - 1];
-                __syncthreads();
-                if (FLAGS && s == 0 && threadIdx.x == 0) {
-                    // every wave has finished step n-1: plane a+n-1 is consumed
-                    flag_store(p.flags + (int64_t)tile * kFlagStride, a + n);
-                }
-                const Real up = buf[wave > 0 ? wave - 1 : 0][1][lane];
-                const Real dn = buf[wave < W - 1 ? wave + 1 : W - 1][0][lane];
-                const bool bnd = BND && ((pe == 0) || (pe == g.nz + 1));
-                // Row by row; `above` keeps the old value of row r-1.
-                Real above = up;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const Real xo = x[r];
-                    const Real below = (r == R - 1) ? dn : x[r < R - 1 ? r + 1 : 0];
-                    const Real inpl = ((from_left(xo) + from_right(xo)) + above) + below;
-                    Real e;
-                    if (bnd) {
-                        e = C[s][r];
-                    } else {
-                        Real sum = P[s][r] + xo;
-                        if (RHS) sum = sum + (Real)rq[RHS ? s : 0][r];
-                        e = sum * c6;
-                        if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
-                    }
-                    P[s][r] = inpl + C[s][r];
-                    C[s][r] = xo;
-                    x[r] = e;
-                    above = xo;
-                }
-            }
-        };
-        if (a + n - T <= 0 || a + n - 1 >= g.nz + 1)
-            stages(std::true_type{});
-        else
-            stages(std::false_type{});
-        if (RHS) {
-#pragma unroll
-            for (int s = (RHS ? T : 1) - 1; s > 0; --s)
-#pragma unroll
-                for (int r = 0; r < R; ++r) rq[s][r] = rq[s - 1][r];
-        }
-
-        // x now holds plane pe_T of the last stage.
-        const int pe = a + n - T;
-        if (pe >= k0 && pe < k1) {
-            if (FLAGS) {
-                // Storage plane overwritten by this store, in input-frame
-                // terms; planes outside the box are shift room nobody reads.
-                const int ow = p.dir > 0 ? pe - T : pe + T;
-                const int need = ow + 1;
-                if (ow >= 0 && ow <= g.nz + 1 && known < need) {
-                    int64_t spins = 0;
-                    for (;;) {
-                        int v = kDone;
-                        if (dep >= 0) v = flag_load(p.flags + (int64_t)dep * kFlagStride);
-#pragma unroll
-                        for (int o = 1; o < 8; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
-                        v = __builtin_amdgcn_readfirstlane(v);
-                        if (v >= need) {
-                            known = v;
-                            break;
-                        }
-                        if (++spins > p.spin_limit ||
-                            flag_load(p.err) != 0) {
-                            if (lane == 0) atomicCAS(p.err, 0, 1);
-                            known = kDone;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-                }
-            }
-            if (lane_out) {
-                char* dp = dst_b + (int64_t)pe * plane_bytes;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (row_out[r]) *reinterpret_cast<Real*>(dp + voff[r]) = x[r];
-            }
-        }
-    }
+    // U consecutive steps from n0 (a multiple of U).
+    auto chunk = [&](const int n0, auto bnd_tag) {
+        static_for<U>([&](auto u) {
+            constexpr int k = decltype(u)::value;
+            step(n0 + k, std::integral_constant<int, (k % PF)>{}, bnd_tag);
+        });
+    };
+    // Steps before `head` and from `tail` on may touch a boundary plane.  The
+    // last chunk may run up to U-1 steps past nsteps: they load and store
+    // nothing.
+    const int head = min(nsteps, max(0, 2 * T - a));
+    const int tail = max(head, min(nsteps, g.nz + 2 - a));
+    int n = 0;
+    for (; n < head; n += U) chunk(n, std::true_type{});
+    for (; n + U <= tail; n += U) chunk(n, std::false_type{});
+    for (; n < nsteps; n += U) chunk(n, std::true_type{});
+    store_out(a + n - 2 * T);
     if (FLAGS) {
         __syncthreads();
         if (threadIdx.x == 0) flag_store(p.flags + (int64_t)tile * kFlagStride, kDone);
@@ -324,7 +357,7 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
     constexpr int H = R * W;
     constexpr int OX = 64 - 2 * T;
     constexpr int OY = H - 2 * T;
-    __shared__ Real xch[2][W][2][64];
+    __shared__ Real xch[Xch<Real, T, W>::nbuf][T][W][2][64];
     __shared__ int tile_sh;
 
     for (int iter = 0;; ++iter) {
@@ -436,7 +469,8 @@ hipError_t launch_cfg(const TripParams& p, hipStream_t s)
     X(1, 4, 16) X(2, 4, 16)                                                   \
     X(1, 4, 8) X(2, 4, 8) X(3, 4, 8) X(4, 4, 8) X(5, 4, 8) X(6, 4, 8)          \
     X(1, 2, 16) X(2, 2, 16) X(3, 2, 16) X(4, 2, 16) X(5, 2, 16) X(6, 2, 16)    \
-    X(7, 2, 16) X(8, 2, 16) X(7, 4, 8) X(8, 4, 8)
+    X(7, 2, 16) X(8, 2, 16) X(7, 4, 8) X(8, 4, 8)                             \
+    X(2, 4, 12) X(3, 3, 12) X(4, 3, 12)
 
 template <typename Real, bool RHS>
 hipError_t dispatch(const TripConfig& c, const TripParams& p, hipStream_t s)

@@ -75,9 +75,46 @@ constexpr int kDone = 0x7fffffff;
 
 // Planes in flight per tile (register ring depth).
 #ifndef JACOBI_PREFETCH
-#define JACOBI_PREFETCH 3
+#define JACOBI_PREFETCH 2
 #endif
 constexpr int kPrefetch = JACOBI_PREFETCH;
+
+// Raw buffer accesses (GFX9 buffer resource, stride 0, 32-bit data format).
+// An access whose byte offset is at or past the descriptor's record count is
+// dropped by the hardware: a load returns 0 and a store writes nothing.  Plane
+// loads and stores therefore need no branches, and the compiler can count
+// outstanding memory operations exactly (a branch around a load makes it
+// wait for all of them).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr uint32_t kOob = 0xFFFF0000u;  // past every plane descriptor's range
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                             (int)bytes, kRsrcWord3);
+}
+template <typename Real>
+__device__ __forceinline__ Real buf_load(Rsrc r, uint32_t off);
+template <>
+__device__ __forceinline__ double buf_load<double>(Rsrc r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(Rsrc r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(double v, Rsrc r, uint32_t off)
+{
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(float v, Rsrc r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
 
 // Geometry and pointers of the problem a tile belongs to.
 struct Geo {
