@@ -50,7 +50,7 @@ def parse():
 
 # Default configuration of the headline line; chosen from the measured sweep
 # over t and layouts (the "extra" block reproduces that sweep on every run).
-DEFAULT_T = 3
+DEFAULT_T = 4
 DEFAULT_LAYOUT = "ab"
 
 

@@ -44,11 +44,6 @@ struct TripParams {
     int count;                  // mode 2: number of problems
     const int* parity;          // mode 2: A/B parity word (device memory)
     int rhs_in_table;           // mode 2: FP32 rhs pointers are in the table
-    // pipelined schedule (launch_pipe_f64): edge-row hand-off ring and the
-    // per-tile "steps produced" words
-    unsigned long long* ring;   // [ntiles][T-1][ring_steps][2][64] FP64 bits
-    int ring_steps;             // steps of one tile (>= k1 - a + T)
-    int* produced;              // per tile, stride kFlagStride ints
 };
 
 constexpr int kFlagStride = 32;  // ints per flag (128 B line each)
@@ -65,13 +60,6 @@ hipError_t launch_trip_f64(const TripConfig& cfg, const TripParams& p,
 hipError_t launch_trip_f32(const TripConfig& cfg, const TripParams& p,
                            hipStream_t s);
 bool trip_config_supported(int dtype_f32, const TripConfig& cfg);
-
-// Pipelined schedule (kernels_pipe.hip): tiles without j ghost rows; each
-// stage's window moves up one row per sweep and the two rows a tile needs
-// from the tile above come through `ring` (FP64, A/B layout, no rhs).
-hipError_t launch_pipe_f64(const TripConfig& cfg, const TripParams& p,
-                           hipStream_t s);
-bool pipe_config_supported(const TripConfig& cfg);
 
 // ---- auxiliary kernels (kernels_aux.hip) ----
 hipError_t launch_fill_i32(int* p, int value, int64_t n, hipStream_t s);

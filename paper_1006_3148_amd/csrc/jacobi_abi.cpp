@@ -46,10 +46,11 @@ int hip_fail(hipError_t e, const char* what)
     return fail(JACOBI_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Tile shape per T: the fastest spill-free shape measured at 512^3.
 TripConfig default_cfg(int T)
 {
-    if (T <= 2) return TripConfig{T, 4, 16};
-    if (T <= 6) return TripConfig{T, 4, 8};
+    if (T == 1) return TripConfig{1, 4, 16};
+    if (T == 2 || T == 4 || T == 6) return TripConfig{T, 4, 8};
     return TripConfig{T, 2, 16};
 }
 
@@ -71,7 +72,9 @@ bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
         if (compressed && seg_req < 2 * T) return false;
         p.seg_len = (int)std::min<int64_t>(seg_req, nz2);
     } else {
-        // Minimise (rounds of concurrent tiles) x (planes each tile streams).
+        // Minimise (rounds of concurrent tiles) x (steps of one tile): a tile
+        // of a segment of len planes takes len + 3T - 1 steps (T ghost planes
+        // on each side, and stage T runs 2T-1 steps behind stage 1).
         const int conc = target_tiles > 0 ? target_tiles : kCUs;
         double best = 1e300;
         int best_len = (int)nz2;
@@ -82,7 +85,7 @@ bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
             const int64_t real_segs = (nz2 + len - 1) / len;
             const int64_t tiles = plane_tiles * real_segs;
             const int64_t rounds = (tiles + conc - 1) / conc;
-            const double cost = (double)rounds * (double)(len + 1.5 * T);
+            const double cost = (double)rounds * (double)(len + 3 * T);
             if (cost < best * 0.999) {
                 best = cost;
                 best_len = (int)len;

@@ -62,6 +62,29 @@ __device__ __forceinline__ void static_for(F&& f)
     static_for_impl(std::make_integer_sequence<int, N>{}, f);
 }
 
+// Spin until every dependee's progress word is >= need (or the bounded spin
+// runs out, which raises the error word).  Out of line, so that the rare wait
+// does not split the straight-line step code of the caller.
+__device__ __attribute__((noinline)) int wait_progress(int* flags, int dep, int need,
+                                                      long long spin_limit, int* err)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t spins = 0;
+    for (;;) {
+        int v = kDone;
+        if (dep >= 0) v = flag_load(flags + (int64_t)dep * kFlagStride);
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
+        v = __builtin_amdgcn_readfirstlane(v);
+        if (v >= need) return v;
+        if (++spins > spin_limit || flag_load(err) != 0) {
+            if (lane == 0) atomicCAS(err, 0, 1);
+            return kDone;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
 // Edge-row exchange buffers in LDS: [buffer][stage][wave][top/bottom][lane].
 // Two buffers (one barrier per step) when they fit comfortably, else one
 // buffer and a second barrier per step before it is rewritten.
@@ -146,6 +169,9 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
             dep = (nsg * g.tiles_y + nty) * g.tiles_x + ntx;
     }
     int known = FLAGS ? 0 : kDone;
+    // Dependee progress word loaded one step ahead (before that step's plane
+    // loads), so reading it does not wait for the plane prefetch.
+    int fl_ahead = 0;
 
     // X[s]: the plane stage s+1 consumes in this step (a plane of stage s,
     // produced by stage s in the previous step); X[T]: the plane stage T
@@ -221,33 +247,6 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     // conditional store.
     auto store_out = [&](const int pe) {
         const bool in = pe >= k0 && pe < k1;
-        if (FLAGS && in) {
-            // Storage plane overwritten by this store, in input-frame terms;
-            // planes outside the box are shift room nobody reads.
-            const int ow = p.dir > 0 ? pe - T : pe + T;
-            const int need = ow + 1;
-            if (ow >= 0 && ow <= g.nz + 1 && known < need) {
-                int64_t spins = 0;
-                for (;;) {
-                    int v = kDone;
-                    if (dep >= 0) v = flag_load(p.flags + (int64_t)dep * kFlagStride);
-#pragma unroll
-                    for (int o = 1; o < 8; o <<= 1) v = min(v, __shfl_xor(v, o, 64));
-                    v = __builtin_amdgcn_readfirstlane(v);
-                    if (v >= need) {
-                        known = v;
-                        break;
-                    }
-                    if (++spins > p.spin_limit || flag_load(p.err) != 0) {
-                        if (lane == 0) atomicCAS(p.err, 0, 1);
-                        known = kDone;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            }
-        }
         const Rsrc rd = make_rsrc(dst_b + (int64_t)(in ? pe : k0) * plane_bytes,
                                   in ? plane_b32 : 0u);
 #pragma unroll
@@ -285,10 +284,6 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
             buf[s][wave][1][lane] = X[s][R - 1];
         }
         __syncthreads();
-        if (FLAGS && threadIdx.x == 0) {
-            // every wave has finished step n-1: plane a+n-1 is consumed
-            flag_store(p.flags + (int64_t)tile * kFlagStride, a + n);
-        }
 
         // Stage s+1 receives plane q = a+n-2s of stage s and completes plane
         // q-1.  Descending s, so X[s+1] is overwritten after stage s+2 has
@@ -318,11 +313,56 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
                 C[s][r] = xo;
                 X[s + 1][r] = e;
             }
+            // Keep the stages in order: interleaving them buys no latency
+            // hiding that the R rows do not already give, and costs registers.
+            __builtin_amdgcn_sched_barrier(0);
         }
+    };
+
+    // Compressed grid: before a chunk of U steps, publish this tile's
+    // progress and wait until the dependees have consumed every storage plane
+    // the chunk's stores overwrite.  Done once per chunk, so that the steps
+    // themselves stay straight-line code.
+    auto sync_chunk = [&](const int n0) {
+        if (n0 > 0 && threadIdx.x == 0) {
+            // all waves passed the barrier of step n0-1: planes up to
+            // a+n0-2 are consumed
+            flag_store(p.flags + (int64_t)tile * kFlagStride, a + n0 - 1);
+        }
+        // Stores of this chunk (and the one after its last step): planes
+        // up to a+n0+U-2T of the output.
+        const int pe_hi = min(a + n0 + U - 2 * T, k1 - 1);
+        if (pe_hi >= k0) {
+            // Storage plane overwritten, in input-frame terms; planes outside
+            // the box are shift room nobody reads.
+            const int ow = min(p.dir > 0 ? pe_hi - T : pe_hi + T, g.nz + 1);
+            const int need = ow + 1;
+            if (need > 0 && known < need) {
+                int v0 = fl_ahead;
+#pragma unroll
+                for (int o = 1; o < 8; o <<= 1) v0 = min(v0, __shfl_xor(v0, o, 64));
+                known = max(known, __builtin_amdgcn_readfirstlane(v0));
+            }
+            if (__builtin_expect(need > 0 && known < need, 0))
+                known = wait_progress(p.flags, dep, need, p.spin_limit, p.err);
+        }
+        // Read one chunk ahead, before the chunk's plane loads.
+        fl_ahead = dep >= 0 ? flag_load(p.flags + (int64_t)dep * kFlagStride) : kDone;
+        // The chunk's stores must follow the reads of the progress words.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     };
 
     // U consecutive steps from n0 (a multiple of U).
     auto chunk = [&](const int n0, auto bnd_tag) {
+        if (FLAGS) {
+            sync_chunk(n0);
+        } else {
+            // A fence at every chunk boundary (no instruction at workgroup
+            // scope) keeps the compiler from moving memory operations between
+            // chunks; without it the unrolled steps are interleaved and the
+            // stage state spills.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
         static_for<U>([&](auto u) {
             constexpr int k = decltype(u)::value;
             step(n0 + k, std::integral_constant<int, (k % PF)>{}, bnd_tag);
