@@ -46,12 +46,18 @@ int hip_fail(hipError_t e, const char* what)
     return fail(JACOBI_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Tile shape per T: the fastest spill-free shape measured at 512^3.
+// Tile shape (rows per wave, waves) per T: the fastest shape measured on a
+// 512^3 FP64 box.
 TripConfig default_cfg(int T)
 {
-    if (T == 1) return TripConfig{1, 4, 16};
-    if (T == 2 || T == 4 || T == 6) return TripConfig{T, 4, 8};
-    return TripConfig{T, 2, 16};
+    switch (T) {
+    case 1:
+    case 2: return TripConfig{T, 4, 16};
+    case 3: return TripConfig{T, 4, 12};
+    case 4:
+    case 6: return TripConfig{T, 3, 12};
+    default: return TripConfig{T, 4, 8};
+    }
 }
 
 bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,

@@ -42,7 +42,8 @@ struct TripSet {
 
 // Candidate shapes of the autotuner (all compiled; see the trip kernel).
 const TripConfig kCandidates[] = {
-    {2, 4, 8}, {3, 2, 16}, {3, 4, 8}, {4, 4, 8}, {4, 2, 16}, {5, 2, 16}, {5, 4, 8},
+    {2, 4, 16}, {3, 4, 12}, {3, 2, 16}, {4, 3, 12}, {4, 4, 8}, {5, 4, 8}, {5, 3, 12},
+    {6, 3, 12},
 };
 
 struct WsLayout {

@@ -510,7 +510,8 @@ hipError_t launch_cfg(const TripParams& p, hipStream_t s)
     X(1, 4, 8) X(2, 4, 8) X(3, 4, 8) X(4, 4, 8) X(5, 4, 8) X(6, 4, 8)          \
     X(1, 2, 16) X(2, 2, 16) X(3, 2, 16) X(4, 2, 16) X(5, 2, 16) X(6, 2, 16)    \
     X(7, 2, 16) X(8, 2, 16) X(7, 4, 8) X(8, 4, 8)                             \
-    X(2, 4, 12) X(3, 3, 12) X(4, 3, 12)
+    X(2, 4, 12) X(3, 3, 12) X(4, 3, 12) X(4, 4, 12) X(5, 3, 12) X(5, 4, 12)   \
+    X(6, 3, 12) X(3, 4, 12)
 
 template <typename Real, bool RHS>
 hipError_t dispatch(const TripConfig& c, const TripParams& p, hipStream_t s)

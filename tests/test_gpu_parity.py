@@ -65,6 +65,33 @@ def test_compressed_trips_bitwise(t, dims):
     _assert_same(got, want, "compressed t=%d %s" % (t, dims))
 
 
+def _compiled_shapes():
+    from paper_1006_3148_amd.solver import tile_supported
+    out = []
+    for t in range(1, 9):
+        for rpw in (2, 3, 4):
+            for waves in (8, 12, 16):
+                if tile_supported(t, rpw * waves, rpw):
+                    out.append((t, rpw * waves, rpw))
+    return out
+
+
+@pytest.mark.parametrize("layout", ["ab", "compressed"])
+def test_every_compiled_tile_shape_bitwise(layout):
+    """Each compiled (t, rows, rows per wave) kernel on a box of several tiles
+    in i and j with ragged tails and several k segments."""
+    box = synth.uniform_box(150, 97, 41, seed=300)
+    shapes = _compiled_shapes()
+    assert len(shapes) >= 20
+    for t, rows, rpw in shapes:
+        n = 3 * t + 2
+        print("case %s t=%d rows=%d rpw=%d n=%d" % (layout, t, rows, rpw, n), flush=True)
+        want = oracle.sweeps_f64(box, n)
+        got, info = _run(box, n, t=t, layout=layout, tile_rows=rows,
+                         rows_per_wave=rpw, seg_len=max(2 * t, 13))
+        _assert_same(got, want, "%s t=%d rows=%d rpw=%d" % (layout, t, rows, rpw))
+
+
 def test_single_sweep_config_64cube_100_sweeps():
     box = synth.uniform_box(64, 64, 64, seed=1)
     print("case 64^3 x 100, t=1", flush=True)
