@@ -86,12 +86,12 @@ __device__ __attribute__((noinline)) int wait_progress(int* flags, int dep, int 
 }
 
 // Edge-row exchange buffers in LDS: [buffer][stage][wave][top/bottom][lane].
-// Two buffers (one barrier per step) when they fit comfortably, else one
-// buffer and a second barrier per step before it is rewritten.
+// Two buffers (one barrier per step) when they fit in the 160 KB of LDS of a
+// CU, else one buffer and a second barrier per step before it is rewritten.
 template <typename Real, int T, int W>
 struct Xch {
     static constexpr size_t one = (size_t)T * W * 2 * 64 * sizeof(Real);
-    static constexpr int nbuf = 2 * one <= 96 * 1024 ? 2 : 1;
+    static constexpr int nbuf = 2 * one <= 150 * 1024 ? 2 : 1;
 };
 
 template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE>

@@ -74,3 +74,29 @@ def test_batch_equals_standalone_handles():
         assert _same(b.box(q), j.box())
         j.close()
     b.close()
+
+
+def test_batch_graph_replays_each_match_eager():
+    """Several replays of one captured schedule, with eager work and
+    synchronisation between them; every replay is checked against the same
+    schedule run eagerly."""
+    from paper_1006_3148_amd import JacobiBatch
+    probs = _problems(6, seed=91)
+    boxes = [p[3] for p in probs]
+    print("case batch graph replays", [p[:3] for p in probs], flush=True)
+    g = JacobiBatch(boxes, t=4, use_graph=True)
+    e = JacobiBatch(boxes, t=4, use_graph=False)
+    for rep in range(4):
+        g.sweep(9)
+        e.sweep(9)
+        gl2, _ = g.residual()   # eager work between replays
+        el2, _ = e.residual()
+        g.sync()
+        e.sync()
+        for q in range(len(boxes)):
+            assert _same(g.box(q), e.box(q)), "replay %d problem %d" % (rep, q)
+        assert np.array_equal(np.asarray(gl2), np.asarray(el2))
+    want = oracle.sweeps_f64(boxes[0], 36)
+    assert _same(g.box(0), want)
+    g.close()
+    e.close()
