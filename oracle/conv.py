@@ -223,13 +223,45 @@ def forward(theta, box, levels, round_bf16=True):
     return out, (cache, w, p)
 
 
-def loss_and_grad(theta, box, target, levels, round_bf16=True):
-    """MSE loss and its gradient with respect to the flat parameters."""
+LOW_MODES = tuple((p, q, r) for p in (1, 2) for q in (1, 2) for r in (1, 2))
+
+
+def low_mode(shape, pqr):
+    """Discrete sine mode sin(p pi i/(n+1)) sin(q pi j/(n+1)) sin(r pi k/(n+1))
+    on the interior cells (k, j, i) = 1..n of a (nz, ny, nx) field."""
+    nz, ny, nx = shape
+    p, q, r = pqr
+    si = np.sin(np.pi * p * np.arange(1, nx + 1) / (nx + 1))
+    sj = np.sin(np.pi * q * np.arange(1, ny + 1) / (ny + 1))
+    sk = np.sin(np.pi * r * np.arange(1, nz + 1) / (nz + 1))
+    return sk[:, None, None] * sj[None, :, None] * si[None, None, :]
+
+
+def low_mode_coeffs(e):
+    """a_m = mean over the cells of e * v_m for the modes in LOW_MODES."""
+    return np.array([np.mean(e * low_mode(e.shape, m)) for m in LOW_MODES])
+
+
+def loss_and_grad(theta, box, target, levels, round_bf16=True, low_weight=0.0):
+    """Loss and its gradient with respect to the flat parameters.
+
+    loss = mean((out - target)^2) + low_weight * sum_m a_m^2, with a_m the
+    mean of (out - target) * v_m over the eight smoothest discrete sine modes
+    v_m (p, q, r in {1, 2}).  The Jacobi iteration removes exactly these error
+    components slowest (their decay factor per sweep is closest to 1), so
+    weighting them sets the sweeps a guess saves; low_weight = 0 is plain
+    MSE.
+    """
     out, (cache, w, p) = forward(theta, box, levels, round_bf16)
     n = out.size
     diff = out - target
     loss = float(np.sum(diff * diff) / n)
     dout = 2.0 * diff / n
+    if low_weight:
+        a = low_mode_coeffs(diff)
+        loss += float(low_weight * np.sum(a * a))
+        for am, m in zip(a, LOW_MODES):
+            dout = dout + (2.0 * low_weight * am / n) * low_mode(diff.shape, m)
     g = {}
     x = cache["last"]
     g["head.w"] = np.einsum("zyx,zyxc->c", dout, x)

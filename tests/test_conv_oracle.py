@@ -119,3 +119,41 @@ def test_adam_matches_torch():
         pt.grad = torch.from_numpy(g.copy())
         opt.step()
     assert np.allclose(th, pt.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_low_mode_coefficients_closed_form():
+    """The discrete sines are orthogonal: for e = sum_m b_m v_m over the eight
+    modes, a_m = b_m * prod over axes of (n+1)/(2n)."""
+    shape = (7, 5, 6)
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(len(cv.LOW_MODES))
+    e = sum(bm * cv.low_mode(shape, m) for bm, m in zip(b, cv.LOW_MODES))
+    scale = np.prod([(d + 1) / (2.0 * d) for d in shape])
+    assert np.allclose(cv.low_mode_coeffs(e), b * scale, rtol=1e-12, atol=1e-14)
+    # a higher mode has no projection on them
+    hi = cv.low_mode(shape, (3, 1, 2))
+    assert np.allclose(cv.low_mode_coeffs(hi), 0.0, atol=1e-14)
+
+
+def test_low_mode_loss_gradient_matches_finite_differences():
+    levels, n = 2, 8
+    rng = np.random.default_rng(12)
+    box = rng.random((n + 2, n + 2, n + 2))
+    target = rng.random((n, n, n))
+    theta = cv.init_params(levels, seed=13) + 0.05 * rng.standard_normal(
+        cv.init_params(levels, seed=13).size)
+    wlow = 50.0
+    loss, g, out = cv.loss_and_grad(theta, box, target, levels, round_bf16=False,
+                                    low_weight=wlow)
+    a = cv.low_mode_coeffs(out - target)
+    assert abs(loss - (np.mean((out - target) ** 2) + wlow * np.sum(a * a))) <= 1e-12 * loss
+    idx = np.concatenate([rng.choice(theta.size, 30, replace=False),
+                          [theta.size - 1, theta.size - 2]])
+    eps = 1e-6
+    for q in idx:
+        tp = theta.copy(); tp[q] += eps
+        tm = theta.copy(); tm[q] -= eps
+        lp = cv.loss_and_grad(tp, box, target, levels, round_bf16=False, low_weight=wlow)[0]
+        lm = cv.loss_and_grad(tm, box, target, levels, round_bf16=False, low_weight=wlow)[0]
+        fd = (lp - lm) / (2 * eps)
+        assert abs(fd - g[q]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (q, fd, g[q])
