@@ -60,6 +60,15 @@ int jg_forward(jg_net *h, const double *box, float *out);
  * stream is synchronized and the loss written to it. */
 int jg_backward(jg_net *h, const float *target, double *loss);
 
+/* Weight W >= 0 of an extra loss term used by jg_backward from the next call
+ * on: loss = mean((out-target)^2) + W * sum_m a_m^2, where a_m is the mean of
+ * (out - target) * v_m over the interior and v_m(i,j,k) =
+ * sin(pi p i/(n+1)) sin(pi q j/(n+1)) sin(pi r k/(n+1)) for p,q,r in {1,2}
+ * (the eight discrete sine modes the Jacobi iteration of Sect. 1.1 damps
+ * slowest; not a quantity of the paper).  0 (the default) is plain MSE.
+ * JACOBI_EINVAL for a null handle or a weight outside [0, 1e12]. */
+int jg_set_low_mode_weight(jg_net *h, double weight);
+
 int jg_zero_grads(jg_net *h);
 
 /* Adam step on params with grads (bias-corrected, step >= 1). */

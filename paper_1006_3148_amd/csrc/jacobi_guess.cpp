@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <new>
 #include <string>
 #include <vector>
@@ -22,7 +23,7 @@ struct Layout {
     size_t total = 0;
     // byte offsets
     size_t w = 0, wt = 0, woff = 0, in = 0, out = 0, blend = 0, loss = 0, lpart = 0,
-           gpart = 0, wpart = 0;
+           gpart = 0, wpart = 0, sines = 0, mpart = 0, acoef = 0;
     std::vector<size_t> ea, eb, dn, sm, da, db, ga, gb, gs;
 };
 
@@ -52,6 +53,9 @@ bool plan(int64_t n, int L, Layout* lay)
     l.lpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 8);
     l.gpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 17 * 4);
     l.wpart = add(off, (size_t)512 * (kConvW + kC) * 4);
+    l.sines = add(off, (size_t)2 * n * 4);
+    l.mpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 8 * 8);
+    l.acoef = add(off, 8 * 8);
     for (int lev = 0; lev < L; ++lev) {
         l.ea.push_back(add(off, vox(lev) * kC * 2));
         l.eb.push_back(add(off, vox(lev) * kC * 2));
@@ -110,6 +114,8 @@ struct jg_net_s {
     Layout lay;
     Index ix;
     std::vector<int64_t> woff_host;
+    std::vector<float> sines_host;
+    float low_weight = 0.f;  // weight of the low-mode term of the loss
 };
 
 namespace {
@@ -178,8 +184,18 @@ int jg_create(int64_t n, int32_t levels, float* params, float* grads, float* ada
     h->ix = layer_index(levels);
     h->woff_host.resize(h->nl);
     for (int q = 0; q < h->nl; ++q) h->woff_host[q] = (int64_t)q * kConvP;
+    // S_p(i) = sin(pi p (i+1)/(n+1)), p = 1, 2: the sine modes of the
+    // low-mode loss term.
+    h->sines_host.resize(2 * n);
+    for (int p = 1; p <= 2; ++p)
+        for (int64_t i = 0; i < n; ++i)
+            h->sines_host[(p - 1) * n + i] =
+                (float)std::sin(M_PI * p * (double)(i + 1) / (double)(n + 1));
     hipError_t e = hipMemcpyAsync(at<int64_t>(h, l.woff), h->woff_host.data(),
                                   sizeof(int64_t) * h->nl, hipMemcpyHostToDevice, h->s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(F(h, l.sines), h->sines_host.data(), sizeof(float) * 2 * n,
+                           hipMemcpyHostToDevice, h->s);
     if (e == hipSuccess) e = hipStreamSynchronize(h->s);
     if (e != hipSuccess) {
         delete h;
@@ -227,8 +243,8 @@ int jg_forward(jg_net* h, const double* box, float* out)
     const float* hw = h->params + (size_t)h->nl * kConvP;
     const int64_t nv = h->n * h->n * h->n;
     if (e == hipSuccess)
-        e = head(x, nv, hw, hw + kC, F(h, l.blend), F(h, l.out), nullptr, nullptr, nullptr,
-                 nullptr, nullptr, nullptr, nullptr, h->s);
+        e = head(x, nv, (int)h->n, hw, hw + kC, F(h, l.blend), F(h, l.out), nullptr,
+                 nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, LowModeLoss{}, h->s);
     if (e == hipSuccess && out)
         e = hipMemcpyAsync(out, F(h, l.out), nv * sizeof(float), hipMemcpyDeviceToDevice, h->s);
     if (e != hipSuccess) return hip_fail(e, "network forward");
@@ -248,10 +264,15 @@ int jg_backward(jg_net* h, const float* target, double* loss)
     float* wpart = F(h, l.wpart);
     const uint16_t* last = A(h, l.db[0]);
     // head: dx into ga[0] (masked by the last ReLU output), head gradients
-    hipError_t e = head(last, nv, hw, hw + kC, F(h, l.blend), F(h, l.out), target,
+    LowModeLoss low;
+    low.weight = h->low_weight;
+    low.sines = F(h, l.sines);
+    low.mpart = at<double>(h, l.mpart);
+    low.acoef = at<double>(h, l.acoef);
+    hipError_t e = head(last, nv, (int)h->n, hw, hw + kC, F(h, l.blend), F(h, l.out), target,
                         F(h, l.ga[0]),
                         at<double>(h, l.lpart), F(h, l.gpart), at<double>(h, l.loss),
-                        gparam_head, gparam_head + kC, h->s);
+                        gparam_head, gparam_head + kC, low, h->s);
     // decoder, from level 0 up: ga[lev] holds the gradient of dec_b's output
     for (int lev = 0; lev <= L - 2 && e == hipSuccess; ++lev) {
         const int d = (int)(h->n >> lev);
@@ -304,6 +325,14 @@ int jg_backward(jg_net* h, const float* target, double* loss)
         if (e == hipSuccess) e = hipStreamSynchronize(h->s);
         if (e != hipSuccess) return hip_fail(e, "loss copy");
     }
+    return JACOBI_OK;
+}
+
+int jg_set_low_mode_weight(jg_net* h, double weight)
+{
+    if (!h) return fail(JACOBI_EINVAL, "null handle");
+    if (!(weight >= 0.0) || weight > 1e12) return fail(JACOBI_EINVAL, "weight must be in [0, 1e12]");
+    h->low_weight = (float)weight;
     return JACOBI_OK;
 }
 

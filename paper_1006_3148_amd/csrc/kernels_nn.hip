@@ -329,19 +329,35 @@ __global__ __launch_bounds__(256) void up_bwd_kernel(const float* __restrict__ d
 }
 
 // ------------------------------------------------------------- head ----
-// out = blend + hw . x + hb (FP32).  With a target: per-block partial sums of
-// (out - target)^2 and dout = 2 (out - target) / nvox written to dx as
-// dx[v][c] = dout * hw[c] (masked by x > 0), and per-block partials of
-// dhw[c] = sum dout x[c], dhb = sum dout.
+// out = blend + hw . x + hb (FP32).  The loss is mean((out - target)^2)
+// plus, optionally, W sum_m a_m^2 with a_m = mean((out - target) v_m) over
+// the eight sine modes v_m(i,j,k) = S_p(i) S_q(j) S_r(k), p,q,r in {1,2}
+// (S_p(i) = sin(pi p (i+1)/(n+1)), mode index m = 4(p-1) + 2(q-1) + (r-1)).
+//
+// MODE 0: forward; with a target also the plain-MSE backward in the same
+//         pass: dout = 2 (out - target) / nvox, dx[v][c] = dout hw[c] (masked
+//         by x > 0), per-block partials of the loss and of dhw, dhb.
+// MODE 1: forward, loss partials and per-block partials of sum (out-target) v_m.
+// MODE 2: backward after MODE 1 and the mode reduction: dout = 2 (out -
+//         target) / nvox + (2 W / nvox) sum_m a_m v_m, then dx and partials.
+__device__ __forceinline__ float mode_value(const float* sines, int n, int64_t v, int m)
+{
+    const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / ((int64_t)n * n));
+    const int p = m >> 2, q = (m >> 1) & 1, r = m & 1;
+    return sines[p * n + i] * sines[q * n + j] * sines[r * n + k];
+}
+
+template <int MODE>
 __global__ __launch_bounds__(256) void head_kernel(
-    const uint16_t* __restrict__ x, int64_t nvox, const float* __restrict__ hw,
+    const uint16_t* __restrict__ x, int64_t nvox, int n, const float* __restrict__ hw,
     const float* __restrict__ hb, const float* __restrict__ blend,
     float* __restrict__ out, const float* __restrict__ target,
     float* __restrict__ dx, double* __restrict__ loss_part,
-    float* __restrict__ gpart)
+    float* __restrict__ gpart, const float* __restrict__ sines,
+    double* __restrict__ mpart, const double* __restrict__ acoef, float wlow)
 {
-    __shared__ double sl[256];
-    __shared__ float sg[17][256];
+    __shared__ double sl[MODE == 1 ? 9 : 1][256];
+    __shared__ float sg[MODE == 1 ? 1 : 17][256];
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float xc[16];
     float o = 0.f;
@@ -354,42 +370,96 @@ __global__ __launch_bounds__(256) void head_kernel(
             xc[2 * q] = bf2f((uint16_t)(wds[q] & 0xffff));
             xc[2 * q + 1] = bf2f((uint16_t)(wds[q] >> 16));
         }
-        o = hb[0];
+        if (MODE == 2) {
+            o = out[v];
+        } else {
+            o = hb[0];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) o += hw[c] * xc[c];
-        o += blend[v];
-        if (out) out[v] = o;
+            for (int c = 0; c < 16; ++c) o += hw[c] * xc[c];
+            o += blend[v];
+            if (out) out[v] = o;
+        }
     } else {
 #pragma unroll
         for (int c = 0; c < 16; ++c) xc[c] = 0.f;
     }
     if (!target) return;
+    const float diff = v < nvox ? o - target[v] : 0.f;
+    if (MODE == 1) {
+        sl[0][threadIdx.x] = (double)diff * diff;
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            sl[1 + m][threadIdx.x] =
+                v < nvox ? (double)diff * (double)mode_value(sines, n, v, m) : 0.0;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) {
+#pragma unroll
+                for (int m = 0; m < 9; ++m) sl[m][threadIdx.x] += sl[m][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            loss_part[blockIdx.x] = sl[0][0];
+            for (int m = 0; m < 8; ++m) mpart[(int64_t)blockIdx.x * 8 + m] = sl[1 + m][0];
+        }
+        return;
+    }
     double l = 0.0;
     float g = 0.f;
     if (v < nvox) {
-        const float diff = o - target[v];
         l = (double)diff * diff;
         g = 2.f * diff / (float)nvox;
+        if (MODE == 2) {
+            float lowsum = 0.f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) lowsum += (float)acoef[m] * mode_value(sines, n, v, m);
+            g += 2.f * wlow * lowsum / (float)nvox;
+        }
 #pragma unroll
         for (int c = 0; c < 16; ++c)
             dx[v * 16 + c] = (xc[c] > 0.f) ? g * hw[c] : 0.f;
     }
-    sl[threadIdx.x] = l;
+    sl[0][threadIdx.x] = l;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) sg[c][threadIdx.x] = g * xc[c];
-    sg[16][threadIdx.x] = g;
+    for (int c = 0; c < 16; ++c) sg[MODE == 1 ? 0 : c][threadIdx.x] = g * xc[c];
+    sg[MODE == 1 ? 0 : 16][threadIdx.x] = g;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            sl[threadIdx.x] += sl[threadIdx.x + s];
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sl[0][threadIdx.x] += sl[0][threadIdx.x + w];
 #pragma unroll
-            for (int c = 0; c < 17; ++c) sg[c][threadIdx.x] += sg[c][threadIdx.x + s];
+            for (int c = 0; c < 17; ++c)
+                sg[MODE == 1 ? 0 : c][threadIdx.x] += sg[MODE == 1 ? 0 : c][threadIdx.x + w];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        loss_part[blockIdx.x] = sl[0];
-        for (int c = 0; c < 17; ++c) gpart[(int64_t)blockIdx.x * 17 + c] = sg[c][0];
+        if (MODE == 0) loss_part[blockIdx.x] = sl[0][0];
+        for (int c = 0; c < 17; ++c)
+            gpart[(int64_t)blockIdx.x * 17 + c] = sg[MODE == 1 ? 0 : c][0];
+    }
+}
+
+// a_m = (sum of the per-block partials, fixed order) / nvox; adds
+// W sum_m a_m^2 to the loss already summed by sum_loss_kernel.
+__global__ void mode_reduce_kernel(const double* __restrict__ mpart, int blocks,
+                                   int64_t nvox, float wlow, double* __restrict__ acoef,
+                                   double* __restrict__ loss)
+{
+    __shared__ double a[8];
+    const int m = threadIdx.x;
+    if (m < 8) {
+        double s = 0.0;
+        for (int b = 0; b < blocks; ++b) s += mpart[(int64_t)b * 8 + m];
+        a[m] = s / (double)nvox;
+        acoef[m] = a[m];
+    }
+    __syncthreads();
+    if (m == 0) {
+        double q = 0.0;
+        for (int k = 0; k < 8; ++k) q += a[k] * a[k];
+        loss[0] += (double)wlow * q;
     }
 }
 
@@ -567,19 +637,33 @@ hipError_t up_bwd(const float* ds, float* dx, int d, const uint16_t* mask, hipSt
 
 int head_blocks(int64_t nvox) { return blocks_for(nvox, 256); }
 
-hipError_t head(const uint16_t* x, int64_t nvox, const float* hw, const float* hb,
+hipError_t head(const uint16_t* x, int64_t nvox, int n, const float* hw, const float* hb,
                 const float* blend, float* out, const float* target, float* dx,
                 double* loss_part, float* gpart, double* loss, float* ghw, float* ghb,
-                hipStream_t s)
+                const LowModeLoss& low, hipStream_t s)
 {
     const int blocks = head_blocks(nvox);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks), dim3(256), 0, s, x, nvox, hw, hb, blend,
-                       out, target, dx, loss_part, gpart);
-    if (target) {
+    if (!target || low.weight == 0.f) {
+        hipLaunchKernelGGL((head_kernel<0>), dim3(blocks), dim3(256), 0, s, x, nvox, n, hw,
+                           hb, blend, out, target, dx, loss_part, gpart, low.sines,
+                           low.mpart, low.acoef, low.weight);
+        if (target)
+            hipLaunchKernelGGL(sum_loss_kernel, dim3(1), dim3(256), 0, s, loss_part, blocks,
+                               nvox, loss);
+    } else {
+        hipLaunchKernelGGL((head_kernel<1>), dim3(blocks), dim3(256), 0, s, x, nvox, n, hw,
+                           hb, blend, out, target, dx, loss_part, gpart, low.sines,
+                           low.mpart, low.acoef, low.weight);
         hipLaunchKernelGGL(sum_loss_kernel, dim3(1), dim3(256), 0, s, loss_part, blocks, nvox,
                            loss);
-        hipLaunchKernelGGL(head_grad_kernel, dim3(1), dim3(64), 0, s, gpart, blocks, ghw, ghb);
+        hipLaunchKernelGGL(mode_reduce_kernel, dim3(1), dim3(64), 0, s, low.mpart, blocks,
+                           nvox, low.weight, low.acoef, loss);
+        hipLaunchKernelGGL((head_kernel<2>), dim3(blocks), dim3(256), 0, s, x, nvox, n, hw,
+                           hb, blend, out, target, dx, loss_part, gpart, low.sines,
+                           low.mpart, low.acoef, low.weight);
     }
+    if (target)
+        hipLaunchKernelGGL(head_grad_kernel, dim3(1), dim3(64), 0, s, gpart, blocks, ghw, ghb);
     return hipGetLastError();
 }
 

@@ -25,10 +25,19 @@ hipError_t up_add(const uint16_t* x, const uint16_t* skip, uint16_t* out, int d,
 hipError_t up_bwd(const float* ds, float* dx, int d, const uint16_t* mask,
                   hipStream_t s);
 int head_blocks(int64_t nvox);
-hipError_t head(const uint16_t* x, int64_t nvox, const float* hw, const float* hb,
+// Optional low-mode term of the loss: weight (0 = plain MSE), the sine tables
+// S_p(i), p = 1, 2 (2n floats), per-block mode partials (8 doubles per head
+// block) and the eight mode coefficients.
+struct LowModeLoss {
+    float weight = 0.f;
+    const float* sines = nullptr;
+    double* mpart = nullptr;
+    double* acoef = nullptr;
+};
+hipError_t head(const uint16_t* x, int64_t nvox, int n, const float* hw, const float* hb,
                 const float* blend, float* out, const float* target, float* dx,
                 double* loss_part, float* gpart, double* loss, float* ghw, float* ghb,
-                hipStream_t s);
+                const LowModeLoss& low, hipStream_t s);
 hipError_t write_guess(const float* out, int n, double* box, hipStream_t s);
 hipError_t prep_weights(const float* params, const int64_t* woff, int layers,
                         uint16_t* w, uint16_t* wt, hipStream_t s);

@@ -20,6 +20,7 @@ _SIGS = {
                    ctypes.c_void_p, ctypes.POINTER(_h)], ctypes.c_int),
     "jg_forward": ([_h, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "jg_backward": ([_h, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "jg_set_low_mode_weight": ([_h, ctypes.c_double], ctypes.c_int),
     "jg_zero_grads": ([_h], ctypes.c_int),
     "jg_adam": ([_h, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                  ctypes.c_int64], ctypes.c_int),
@@ -96,6 +97,10 @@ class GuessNet:
         check(lib.jg_backward(self._h, target.data_ptr(),
                               ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
+
+    def set_low_mode_weight(self, weight: float) -> None:
+        """Weight of the low-mode term of the training loss (0: plain MSE)."""
+        check(lib.jg_set_low_mode_weight(self._h, float(weight)))
 
     def zero_grads(self) -> None:
         check(lib.jg_zero_grads(self._h))

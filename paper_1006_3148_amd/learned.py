@@ -241,6 +241,8 @@ def main(argv=None):
     ap.add_argument("--eval", type=int, default=64)
     ap.add_argument("--check-every", type=int, default=256)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--low-weight", type=float, default=0.0,
+                    help="weight of the low-mode term of the loss (0: plain MSE)")
     ap.add_argument("--time-only", action="store_true")
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
@@ -271,6 +273,8 @@ def main(argv=None):
         return report
     U, basis = solve_basis(a.n, a.pmax, check_every=512)
     log("basis: " + json.dumps(basis))
+    net.set_low_mode_weight(a.low_weight)
+    report["low_weight"] = a.low_weight
     seeds = list(range(1000, 1000 + a.train))
     val = list(range(1000 + a.train, 1000 + a.train + a.val))
     tr = train(net, U, a.n, a.pmax, seeds, a.epochs, a.lr, a.accum, val, log)

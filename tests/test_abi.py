@@ -123,6 +123,8 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.jacobi_residual(None, ctypes.byref(l2), None) == -1
     assert lib.jacobi_sync(None) == -1
     assert lib.jacobi_destroy(None) == 0
+    from paper_1006_3148_amd import guess
+    assert guess.lib.jg_set_low_mode_weight(None, 1.0) == -1
 
 
 def test_tile_menu():

@@ -55,6 +55,36 @@ def test_forward_and_gradient_match_oracle(n, levels):
     net.close()
 
 
+@pytest.mark.parametrize("weight", [0.0, 40.0])
+def test_low_mode_loss_matches_oracle(weight):
+    """Loss with the low-mode term (and plain MSE again after it is switched
+    back off), on a target with a large smooth component."""
+    import torch
+    from paper_1006_3148_amd import GuessNet
+    n, levels = 16, 3
+    print("case guess low-mode weight=%g" % weight, flush=True)
+    theta = _theta(levels, 4)
+    box = synth.sine_face_box(n, n, n, seed=6)
+    rng = np.random.default_rng(10)
+    target = (0.3 * rng.standard_normal((n, n, n))
+              + 2.0 * cv.low_mode((n, n, n), (1, 1, 1))
+              - 1.0 * cv.low_mode((n, n, n), (2, 1, 2))).astype(np.float32)
+    net = GuessNet(n, levels, theta)
+    bt = torch.from_numpy(box).cuda()
+    tt = torch.from_numpy(target).cuda()
+    for w in (weight, 0.0):
+        net.set_low_mode_weight(w)
+        net.forward(bt)
+        net.zero_grads()
+        loss = net.backward(tt)
+        g = net.grads.cpu().numpy().astype(np.float64)
+        lref, gref, _ = cv.loss_and_grad(theta, box, target.astype(np.float64), levels,
+                                         round_bf16=True, low_weight=w)
+        assert abs(loss - lref) <= 2e-3 * abs(lref), (w, loss, lref)
+        assert _rel(g, gref) < 3e-2, (w, _rel(g, gref))
+    net.close()
+
+
 def test_adam_step_matches_oracle():
     import torch
     from paper_1006_3148_amd import GuessNet
