@@ -533,18 +533,28 @@ __global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, in
         p[q] = 0.f;
 }
 
-// Head parameter gradients from per-block partials (fixed order).
-__global__ void head_grad_kernel(const float* __restrict__ gpart, int blocks,
-                                 float* __restrict__ ghw, float* __restrict__ ghb)
+// Head parameter gradients from per-block partials: one workgroup per
+// component, strided partial sums then a tree, both in a fixed order.
+__global__ __launch_bounds__(256) void head_grad_kernel(const float* __restrict__ gpart,
+                                                        int blocks, float* __restrict__ ghw,
+                                                        float* __restrict__ ghb)
 {
-    const int c = threadIdx.x;
-    if (c >= 17) return;
-    float s = 0.f;
-    for (int b = 0; b < blocks; ++b) s += gpart[(int64_t)b * 17 + c];
-    if (c < 16)
-        ghw[c] += s;
-    else
-        ghb[0] += s;
+    __shared__ float sh[256];
+    const int c = blockIdx.x;  // 0..15: hw, 16: hb
+    float a = 0.f;
+    for (int b = threadIdx.x; b < blocks; b += 256) a += gpart[(int64_t)b * 17 + c];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < 16)
+            ghw[c] += sh[0];
+        else
+            ghb[0] += sh[0];
+    }
 }
 
 int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
@@ -663,7 +673,7 @@ hipError_t head(const uint16_t* x, int64_t nvox, int n, const float* hw, const f
                            low.mpart, low.acoef, low.weight);
     }
     if (target)
-        hipLaunchKernelGGL(head_grad_kernel, dim3(1), dim3(64), 0, s, gpart, blocks, ghw, ghb);
+        hipLaunchKernelGGL(head_grad_kernel, dim3(17), dim3(256), 0, s, gpart, blocks, ghw, ghb);
     return hipGetLastError();
 }
 
