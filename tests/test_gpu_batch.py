@@ -100,3 +100,18 @@ def test_batch_graph_replays_each_match_eager():
     assert _same(g.box(0), want)
     g.close()
     e.close()
+
+
+def test_batch_solve_counts_match_oracle():
+    from paper_1006_3148_amd import JacobiBatch
+    boxes = [synth.sine_face_box(n1, n2, n3, seed=60 + q)
+             for q, (n1, n2, n3) in enumerate([(20, 17, 23), (31, 12, 18), (9, 9, 9),
+                                                (26, 30, 14)])]
+    print("case batch solve", [b.shape for b in boxes], flush=True)
+    b = JacobiBatch(boxes, t=3)
+    done, fin = b.solve(1e-8, 20000, 32)
+    b.close()
+    for q, box in enumerate(boxes):
+        _, wdone, wrn, _ = oracle.solve_to_tol(box, 1e-8, check_every=32, max_sweeps=20000)
+        assert done[q] == wdone, (q, done[q], wdone)
+        assert abs(fin[q] - wrn) <= 1e-12 * wrn

@@ -141,3 +141,59 @@ def test_f32_refined_matches_oracle(layout):
     got = j.box()
     j.close()
     _assert_same(got, want, "f32 refined " + layout)
+
+
+@pytest.mark.parametrize("layout", ["ab", "compressed"])
+def test_solve_to_tolerance_matches_oracle(layout):
+    """Run to ||r|| <= 1e-8 ||r0|| checking every 64 sweeps: the same sweep
+    count and the same field, bit for bit, as the oracle's driver."""
+    from paper_1006_3148_amd import Jacobi
+    box = synth.sine_face_box(30, 26, 22, seed=3)
+    print("case solve %s 30x26x22" % layout, flush=True)
+    want, wdone, wrn, r0 = oracle.solve_to_tol(box, 1e-8, check_every=64, max_sweeps=20000)
+    j = Jacobi(box, t=4, layout=layout)
+    done, fin = j.solve(1e-8, 20000, 64)
+    got = j.box()
+    j.close()
+    assert done == wdone and 0 < done < 20000
+    _assert_same(got, want, "solve %s" % layout)
+    assert abs(fin - wrn) <= 1e-12 * wrn
+    # an unreachable tolerance stops at max_sweeps (not a multiple of the check)
+    want2, wdone2, _, _ = oracle.solve_to_tol(box, 1e-300, check_every=64, max_sweeps=150)
+    j = Jacobi(box, t=4, layout=layout)
+    done2, _ = j.solve(1e-300, 150, 64)
+    got2 = j.box()
+    j.close()
+    assert done2 == wdone2 == 150
+    _assert_same(got2, want2, "solve cap %s" % layout)
+
+
+def test_compressed_spin_bound_reports_timeout_and_recovers():
+    """With the progress-wait spin bound forced to 1 from the host, a waiting
+    tile gives up, the kernel still exits normally and the call reports
+    JACOBI_ETIMEOUT; a handle made afterwards with the normal bound is exact."""
+    import os
+    from paper_1006_3148_amd import Jacobi
+    from paper_1006_3148_amd._lib import JacobiError
+    box = synth.uniform_box(300, 200, 90, seed=21)
+    print("case spin bound 1, compressed 300x200x90", flush=True)
+    timed_out = False
+    os.environ["JACOBI_SPIN_LIMIT"] = "1"
+    try:
+        for _ in range(3):
+            j = Jacobi(box, t=4, layout="compressed", seg_len=8)
+            try:
+                j.sweep(8)
+                j.sync()
+            except JacobiError as e:
+                assert e.code == -5, e
+                timed_out = True
+            j.close()
+            if timed_out:
+                break
+    finally:
+        del os.environ["JACOBI_SPIN_LIMIT"]
+    assert timed_out
+    want = oracle.sweeps_f64(box, 8)
+    got, _ = _run(box, 8, t=4, layout="compressed", seg_len=8)
+    _assert_same(got, want, "after timeout")
