@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--t", type=int, default=0, help="sweeps per trip (0=best)")
     ap.add_argument("--layout", default="", help="ab | compressed ('' = best)")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--tts-only", type=int, default=0, metavar="N",
+                    help="only measure time to 1e-8 at N^3 and print it as JSON")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--quick", action="store_true",
@@ -177,6 +179,10 @@ def main():
         print(json.dumps({"probe": "copy", "bytes_read": a.numel() * 8,
                           "bytes_written": b.numel() * 8, "launches": 5}))
         return
+    if args.tts_only:
+        res = bench_time_to_tol(torch, args.tts_only, args.t or DEFAULT_T)
+        print(json.dumps({"time_to_1e-8": res}), flush=True)
+        return
     n, sweeps = args.n, args.sweeps
     t = args.t or DEFAULT_T
     layout = args.layout or DEFAULT_LAYOUT
@@ -244,6 +250,7 @@ def main():
             extra["n1024_compressed"] = bench_1024(torch, t)
             extra["batched_256"] = bench_batched(torch)
             extra["time_to_1e-8_256"] = bench_time_to_tol(torch, 256, t)
+            extra["time_to_1e-8_512"] = "profiles/time_to_tol_512.json (bench.py --tts-only 512)"
         out["extra"] = extra
 
     if not args.no_cpu:
@@ -308,7 +315,8 @@ def bench_batched(torch, count=256, seed=4, sweeps=500):
 
 def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024):
     """Sweeps and seconds to ||r|| <= 1e-8 ||r0|| from the zero start with
-    sine-mode faces: FP64 blocked (t), FP32-refined, plain FP64 t=1."""
+    sine-mode faces: FP64 blocked (t), FP32-refined, plain FP64 t=1.  Each
+    solve runs in calls of 64 checks (r0 held fixed), printing progress."""
     import synth
     from paper_1006_3148_amd import Jacobi
     box = synth.sine_face_box(n, n, n, seed=3)
@@ -317,14 +325,22 @@ def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024):
                      ("f32_refined", dict(t=t, dtype="f32_refined", inner_sweeps=check)),
                      ("f64_single_sweep", dict(t=1))):
         j = Jacobi(box, **kw)
+        r0, _ = j.residual()
         torch.cuda.synchronize()
         a = time.perf_counter()
-        done, fin = j.solve(rel_tol, 5_000_000, check)
+        total = 0
+        while True:
+            done, fin = j.solve(rel_tol, 64 * check, check, r0)
+            total += done
+            if fin <= rel_tol * r0 or total >= 50_000_000:
+                break
+            print("time-to-tol n=%d %s: %d sweeps, ||r||/||r0|| = %.3e, %.1f s"
+                  % (n, name, total, fin / r0, time.perf_counter() - a),
+                  file=sys.stderr, flush=True)
         dt = time.perf_counter() - a
-        r0 = None
         j.close()
-        res[name] = {"sweeps": done, "seconds": round(dt, 3), "final_l2": fin,
-                     "glups": round(n ** 3 * done / dt / 1e9, 1)}
+        res[name] = {"sweeps": total, "seconds": round(dt, 3), "final_l2": fin,
+                     "glups": round(n ** 3 * total / dt / 1e9, 1)}
     torch.cuda.empty_cache()
     return res
 
