@@ -247,6 +247,7 @@ def main():
                 tab["%s_t%d" % (lay, tt)] = round(glups(n, sweeps, w), 1)
         extra["glups_by_layout_t_512"] = tab
         if not args.quick:
+            extra["n64_100_sweeps"] = bench_small_64(torch)
             extra["n1024_compressed"] = bench_1024(torch, t)
             extra["batched_256"] = bench_batched(torch)
             extra["time_to_1e-8_256"] = bench_time_to_tol(torch, 256, t)
@@ -310,6 +311,53 @@ def bench_batched(torch, count=256, seed=4, sweeps=500):
         b.close()
     del boxes
     torch.cuda.empty_cache()
+    return res
+
+
+def bench_small_64(torch, sweeps=100, reps=5):
+    """64^3 interior (fits in L2/MALL), 100 single sweeps: launch-latency bound.
+    Eager one launch per sweep (t=1), the same replayed as a captured hipGraph
+    (single-problem and batch paths), and the blocked default for reference."""
+    import synth
+    from paper_1006_3148_amd import Jacobi, JacobiBatch
+    box = synth.uniform_box(64, 64, 64, seed=1)
+    cells = 64 ** 3
+    res = {"n": 64, "sweeps": sweeps}
+
+    def timed(obj):
+        obj.sweep(sweeps)            # warm-up (and capture, for graphs)
+        obj.sync()
+        best = 1e30
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            obj.sweep(sweeps)
+            obj.sync()
+            best = min(best, time.perf_counter() - a)
+        return best
+
+    j = Jacobi(box, t=1)
+    dt = timed(j)
+    j.close()
+    res["eager_t1"] = {"seconds": round(dt, 6), "glups": round(cells * sweeps / dt / 1e9, 1),
+                       "us_per_sweep": round(dt / sweeps * 1e6, 2)}
+    j = Jacobi(box, t=1, use_graph=True)
+    dt = timed(j)
+    j.close()
+    res["graph_t1"] = {"seconds": round(dt, 6), "glups": round(cells * sweeps / dt / 1e9, 1),
+                       "us_per_sweep": round(dt / sweeps * 1e6, 2)}
+    b = JacobiBatch([box], t=1, use_graph=True)
+    dt = timed(b)
+    b.close()
+    res["batch_graph_t1"] = {"seconds": round(dt, 6),
+                             "glups": round(cells * sweeps / dt / 1e9, 1),
+                             "us_per_sweep": round(dt / sweeps * 1e6, 2)}
+    j = Jacobi(box, t=0)
+    dt = timed(j)
+    info = j.info()
+    j.close()
+    res["eager_blocked"] = {"t": info["t"], "seconds": round(dt, 6),
+                            "glups": round(cells * sweeps / dt / 1e9, 1)}
     return res
 
 

@@ -77,7 +77,10 @@ typedef struct {
     int32_t seg_len;     /* k planes per tile segment, 0 = automatic */
     int32_t inner_sweeps;/* JACOBI_F32_REFINED: FP32 sweeps per outer
                             correction step (0 = 32) */
-    int32_t reserved;
+    int32_t use_graph;   /* 1: A/B FP64 jacobi_sweep calls are captured once
+                            per (n_steps, current grid) into a hipGraph on an
+                            internal stream (up to 8 kept) and replayed on
+                            `stream`; 0: every trip is launched eagerly */
     void *grid0;         /* FP64 grid buffer (device); see jacobi_grid_bytes */
     void *grid1;         /* second FP64 grid for JACOBI_LAYOUT_AB, else NULL */
     void *workspace;     /* device scratch owned by the caller */

@@ -134,6 +134,21 @@ struct jacobi_s {
     float* e[2] = {nullptr, nullptr};
     float* rhs = nullptr;
     AuxProblem aux{};         // residual / refinement view of this problem
+    // A/B FP64 graph replay (use_graph): trips are captured on `cap` once per
+    // (sweep count, starting grid) and replayed on `stream`.
+    hipStream_t run = nullptr;  // stream trip launches go to (stream or cap)
+    hipStream_t cap = nullptr;
+    struct Replay {
+        int64_t n;
+        int cur0, cur1;
+        hipGraphExec_t exec;
+    };
+    std::vector<Replay> replays;
+    ~jacobi_s()
+    {
+        for (Replay& r : replays) hipGraphExecDestroy(r.exec);
+        if (cap) hipStreamDestroy(cap);
+    }
 };
 
 namespace {
@@ -243,13 +258,13 @@ hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
     p.spin_limit = h->spin_limit;
     if (mode == 1) {
         hipError_t e = launch_fill_i32(h->flags, 0, (int64_t)pl.ntiles * kFlagStride,
-                                       h->stream);
+                                       h->run);
         if (e != hipSuccess) return e;
-        e = launch_fill_i32(h->ticket, 0, 1, h->stream);
+        e = launch_fill_i32(h->ticket, 0, 1, h->run);
         if (e != hipSuccess) return e;
     }
-    return f32 ? launch_trip_f32(pl.cfg, p, h->stream)
-               : launch_trip_f64(pl.cfg, p, h->stream);
+    return f32 ? launch_trip_f32(pl.cfg, p, h->run)
+               : launch_trip_f64(pl.cfg, p, h->run);
 }
 
 double* grid_origin(jacobi_t* h, int which_off)
@@ -334,6 +349,52 @@ int outer_f32(jacobi_t* h, int64_t m)
                                     h->stream);
     if (e != hipSuccess) return hip_fail(e, "correction launch");
     h->sweeps += m;
+    return JACOBI_OK;
+}
+
+// A/B FP64 sweeps through a captured graph: capture run_f64's trips once per
+// (n, starting grid) on the internal stream, then launch the executable graph
+// on the caller's stream.  At most kMaxReplays graphs are kept; beyond that
+// the sweeps run eagerly.
+constexpr size_t kMaxReplays = 8;
+
+int replay_f64(jacobi_t* h, int64_t n)
+{
+    jacobi_s::Replay* hit = nullptr;
+    for (jacobi_s::Replay& r : h->replays)
+        if (r.n == n && r.cur0 == h->cur) hit = &r;
+    if (!hit) {
+        if (h->replays.size() >= kMaxReplays) return run_f64(h, n);
+        hipError_t e = hipSuccess;
+        if (!h->cap) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "capture stream");
+        const int cur0 = h->cur;
+        const int64_t sweeps0 = h->sweeps;
+        e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        h->run = h->cap;
+        const int rc = run_f64(h, n);
+        h->run = h->stream;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(h->cap, &g);
+        jacobi_s::Replay r{n, cur0, h->cur, nullptr};
+        h->cur = cur0;  // captured, not yet run
+        h->sweeps = sweeps0;
+        if (rc != JACOBI_OK) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        e = hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+        h->replays.push_back(r);
+        hit = &h->replays.back();
+    }
+    hipError_t e = hipGraphLaunch(hit->exec, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    h->cur = hit->cur1;
+    h->sweeps += n;
     return JACOBI_OK;
 }
 
@@ -428,6 +489,7 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     h->px = d->nx + 2 + h->room;
     h->py = h->px * (d->ny + 2 + h->room);
     h->stream = static_cast<hipStream_t>(d->stream);
+    h->run = h->stream;
     h->inner = d->inner_sweeps > 0 ? d->inner_sweeps : 32;
     if (const char* s = std::getenv("JACOBI_SPIN_LIMIT")) {
         long long v = std::atoll(s);
@@ -483,6 +545,9 @@ int jacobi_sweep(jacobi_t* h, int64_t n_steps)
 {
     if (!h) return fail(JACOBI_EINVAL, "null handle");
     if (n_steps < 0) return fail(JACOBI_EINVAL, "n_steps < 0");
+    if (h->d.dtype == JACOBI_F64 && h->d.use_graph && h->d.layout == JACOBI_LAYOUT_AB &&
+        n_steps > 0)
+        return replay_f64(h, n_steps);
     if (h->d.dtype == JACOBI_F64) return run_f64(h, n_steps);
     while (n_steps > 0) {
         const int64_t m = std::min<int64_t>(h->inner, n_steps);

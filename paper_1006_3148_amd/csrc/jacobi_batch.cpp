@@ -168,15 +168,31 @@ int ensure_set(jacobi_batch_t* h, const TripConfig& cfg)
     if (s.ready && s.cfg.R == cfg.R && s.cfg.W == cfg.W) return JACOBI_OK;
     s.host64.assign(h->count, BatchProblem{});
     s.host32.assign(h->count, BatchProblem{});
+    // A batch with plenty of tile columns streams each column's whole k
+    // range in one tile; one with fewer tiles than two per CU splits k into
+    // segments the way a single problem does, so the launch fills the GPU.
+    std::vector<Plan> plans(h->count);
+    int64_t whole = 0;
+    for (int pos = 0; pos < h->count; ++pos) {
+        const int64_t* x = &h->dims[3 * h->order[pos]];
+        if (!make_plan(x[0], x[1], x[2], cfg, 0, false, 1, &plans[pos]))
+            return fail(JACOBI_EUNSUPPORTED, "tile shape t=%d rows=%d cannot cover problem %d",
+                        cfg.T, cfg.R * cfg.W, h->order[pos]);
+        whole += plans[pos].ntiles;
+    }
+    if (whole < 2 * kCUs) {
+        for (int pos = 0; pos < h->count; ++pos) {
+            const int64_t* x = &h->dims[3 * h->order[pos]];
+            if (!make_plan(x[0], x[1], x[2], cfg, 0, false, kCUs, &plans[pos]))
+                return fail(JACOBI_EUNSUPPORTED, "tile shape t=%d rows=%d cannot cover problem %d",
+                            cfg.T, cfg.R * cfg.W, h->order[pos]);
+        }
+    }
     int base = 0;
     for (int pos = 0; pos < h->count; ++pos) {
         const int q = h->order[pos];
         const int64_t* x = &h->dims[3 * q];
-        Plan pl;
-        // Plenty of tiles across a batch: one k segment per tile column.
-        if (!make_plan(x[0], x[1], x[2], cfg, 0, false, 1, &pl))
-            return fail(JACOBI_EUNSUPPORTED, "tile shape t=%d rows=%d cannot cover problem %d",
-                        cfg.T, cfg.R * cfg.W, q);
+        const Plan& pl = plans[pos];
         BatchProblem b{};
         b.px = x[0] + 2;
         b.py = (x[0] + 2) * (x[1] + 2);

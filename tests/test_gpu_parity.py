@@ -197,3 +197,29 @@ def test_compressed_spin_bound_reports_timeout_and_recovers():
     want = oracle.sweeps_f64(box, 8)
     got, _ = _run(box, 8, t=4, layout="compressed", seg_len=8)
     _assert_same(got, want, "after timeout")
+
+
+def test_graph_replay_matches_eager_every_call():
+    """A/B FP64 sweeps replayed from captured graphs (two starting grids, two
+    sweep counts) with eager work and synchronisation between the calls: each
+    call is checked against an eager handle."""
+    from paper_1006_3148_amd import Jacobi
+    box = synth.uniform_box(90, 61, 33, seed=31)
+    print("case graph replay 90x61x33", flush=True)
+    g = Jacobi(box, t=4, use_graph=True)
+    e = Jacobi(box, t=4)
+    total = 0
+    for n in (9, 9, 9, 5, 9, 5):
+        g.sweep(n)
+        e.sweep(n)
+        total += n
+        gl2, _ = g.residual()
+        el2, _ = e.residual()
+        g.sync()
+        e.sync()
+        _assert_same(g.box(), e.box(), "graph after %d sweeps" % total)
+        assert gl2 == el2
+        assert g.info()["sweeps"] == total
+    _assert_same(g.box(), oracle.sweeps_f64(box, total), "graph vs oracle")
+    g.close()
+    e.close()
