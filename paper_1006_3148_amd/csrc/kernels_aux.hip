@@ -51,22 +51,12 @@ __device__ __forceinline__ const AuxProblem* find_rblock(const AuxProblem* tab,
     return tab + lo;
 }
 
-__device__ __forceinline__ double resid_at(const double* __restrict__ c,
-                                           int64_t px, double um, double up,
-                                           double uc)
-{
-    double s = c[-1];
-    s = s + c[1];
-    s = s + c[-px];
-    s = s + c[px];
-    s = s + um;
-    s = s + up;
-    return s - 6.0 * uc;
-}
-
 // Pass 1: k-streaming residual.  Each thread owns one interior column (i, j)
 // of a 64 x 4 tile and one k segment; the k-1 / k / k+1 values stay in
-// registers, the in-plane neighbours come through L1/L2.
+// registers, the in-plane neighbours come through L1/L2.  Planes are taken
+// four at a time with every load of the group issued before any use (plane
+// indices clamped to the box, so there is no branch around a load), which
+// keeps four planes of loads in flight per thread.
 __global__ __launch_bounds__(kRedThreads) void residual_pass1(
     const AuxProblem* __restrict__ tab, int count, AuxProblem one,
     const int* __restrict__ parity, double* __restrict__ partials)
@@ -89,17 +79,36 @@ __global__ __launch_bounds__(kRedThreads) void residual_pass1(
     double sum = 0.0, mx = 0.0;
     if (i <= P->nx && j <= P->ny) {
         const double* col = u + (int64_t)j * px + i;
+        const int kmax = P->nz + 1;
         double um = col[(int64_t)(k0 - 1) * py];
         double uc = col[(int64_t)k0 * py];
-        double up = col[(int64_t)(k0 + 1) * py];
-        for (int k = k0; k < k1; ++k) {
-            const double upp = (k + 2 <= P->nz + 1) ? col[(int64_t)(k + 2) * py] : 0.0;
-            const double r = resid_at(col + (int64_t)k * py, px, um, up, uc);
-            sum = sum + r * r;
-            mx = fmax(mx, fabs(r));
-            um = uc;
-            uc = up;
-            up = upp;
+        for (int k = k0; k < k1; k += 4) {
+            double z[4], w[4], e[4], s_[4], n[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                z[q] = col[(int64_t)min(k + 1 + q, kmax) * py];
+                const double* c = col + (int64_t)min(k + q, kmax) * py;
+                w[q] = c[-1];
+                e[q] = c[1];
+                s_[q] = c[-px];
+                n[q] = c[px];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (k + q < k1) {
+                    double t = w[q];
+                    t = t + e[q];
+                    t = t + s_[q];
+                    t = t + n[q];
+                    t = t + um;
+                    t = t + z[q];
+                    const double r = t - 6.0 * uc;
+                    sum = sum + r * r;
+                    mx = fmax(mx, fabs(r));
+                }
+                um = uc;
+                uc = z[q];
+            }
         }
     }
     block_reduce(sum, mx, sh_sum, sh_max);
