@@ -21,7 +21,9 @@
 //  * stage s consumes in step n what stage s-1 produced in step n-1 (stage s
 //    runs two planes behind stage s-1 instead of one).  The edge rows of all
 //    T stages are then exchanged together, with one barrier per step, and
-//    the T stages of a step are independent chains of arithmetic;
+//    the T stages of a step are independent chains of arithmetic; the rows
+//    that need nothing from other waves are computed while the barrier and
+//    the LDS reads are pending;
 //  * tiles overlap by T cells in i and j and by T planes between k segments
 //    (ghost zones): stage s is exact on a region that shrinks by one cell per
 //    stage, and only the central (64-2T) x (R*W-2T) x seg_len block is stored.
@@ -283,38 +285,54 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
             buf[s][wave][0][lane] = X[s][0];
             buf[s][wave][1][lane] = X[s][R - 1];
         }
-        __syncthreads();
 
         // Stage s+1 receives plane q = a+n-2s of stage s and completes plane
-        // q-1.  Descending s, so X[s+1] is overwritten after stage s+2 has
-        // read it.
+        // q-1 of row r from rows r-1, r, r+1 of X[s]: one update of Eq. (1)
+        // in its fold order, with the k-streaming state of the row.
+        auto update = [&](const int s, const int r, const Real above, const Real below) {
+            const int pe = a + n - 2 * s - 1;
+            const bool bnd = BND && ((pe == 0) || (pe == g.nz + 1));
+            const Real xo = X[s][r];
+            const Real inpl = ((from_left(xo) + from_right(xo)) + above) + below;
+            Real e;
+            if (bnd) {
+                e = C[s][r];
+            } else {
+                Real sum = P[s][r] + xo;
+                if (RHS) sum = sum + (Real)rr[RHS ? 2 * s : 0][r];
+                e = sum * c6;
+                if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
+            }
+            P[s][r] = inpl + C[s][r];
+            C[s][r] = xo;
+            return e;
+        };
+
+        // Rows 1..R-2 of every stage need nothing from the other waves:
+        // computed before the barrier (into Y, since X[s] rows are still read
+        // by the edge rows after it).  Descending s, so that X[s+1] is
+        // overwritten only after stage s+2 has read it.
+        Real Y[T][R > 2 ? R - 2 : 1];
 #pragma unroll
         for (int s = T - 1; s >= 0; --s) {
-            const int pe = a + n - 2 * s - 1;
+#pragma unroll
+            for (int r = 1; r + 1 < R; ++r)
+                Y[s][r - 1] = update(s, r, X[s][r - 1], X[s][r + 1]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+        // Rows 0 and R-1 take their outer neighbours from the waves above
+        // and below.
+#pragma unroll
+        for (int s = T - 1; s >= 0; --s) {
             const Real up = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
             const Real dn = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
-            const bool bnd = BND && ((pe == 0) || (pe == g.nz + 1));
+            const Real e0 = update(s, 0, up, R > 1 ? X[s][R > 1 ? 1 : 0] : dn);
+            const Real e1 = R > 1 ? update(s, R - 1, X[s][R > 1 ? R - 2 : 0], dn) : e0;
+            X[s + 1][0] = e0;
+            X[s + 1][R - 1] = e1;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const Real xo = X[s][r];
-                const Real above = r == 0 ? up : X[s][r > 0 ? r - 1 : 0];
-                const Real below = r == R - 1 ? dn : X[s][r < R - 1 ? r + 1 : 0];
-                const Real inpl = ((from_left(xo) + from_right(xo)) + above) + below;
-                Real e;
-                if (bnd) {
-                    e = C[s][r];
-                } else {
-                    Real sum = P[s][r] + xo;
-                    if (RHS) sum = sum + (Real)rr[RHS ? 2 * s : 0][r];
-                    e = sum * c6;
-                    if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
-                }
-                P[s][r] = inpl + C[s][r];
-                C[s][r] = xo;
-                X[s + 1][r] = e;
-            }
-            // Keep the stages in order: interleaving them buys no latency
-            // hiding that the R rows do not already give, and costs registers.
+            for (int r = 1; r + 1 < R; ++r) X[s + 1][r] = Y[s][r - 1];
             __builtin_amdgcn_sched_barrier(0);
         }
     };
