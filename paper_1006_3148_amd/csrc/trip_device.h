@@ -1,6 +1,6 @@
-// Device helpers shared by the trip kernels (kernels_trip.hip and
-// kernels_pipe.hip).  Included inside an anonymous namespace of each
-// translation unit.
+// Device helpers of the trip kernel (kernels_trip.hip): constants, DPP lane
+// shifts, the XCD-aware tile map, progress-word access and raw buffer loads
+// and stores.
 #pragma once
 
 #include <hip/hip_runtime.h>
