@@ -628,6 +628,9 @@ int jacobi_info(jacobi_t* h, int64_t* sweeps_done, int32_t* t,
 
 int jacobi_destroy(jacobi_t* h)
 {
+    if (!h) return JACOBI_OK;
+    // replayed graphs may still be running on the caller's stream
+    if (!h->replays.empty()) (void)hipStreamSynchronize(h->stream);
     delete h;
     return JACOBI_OK;
 }

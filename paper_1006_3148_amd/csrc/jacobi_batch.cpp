@@ -649,7 +649,8 @@ int jacobi_batch_sync(jacobi_batch_t* h)
 int jacobi_batch_destroy(jacobi_batch_t* h)
 {
     if (!h) return JACOBI_OK;
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    // work, graphs included, may still be running on the caller's stream
+    if (h->stream || !h->graphs.empty()) (void)hipStreamSynchronize(h->stream);
     for (auto& kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipGraph_t g : h->graph_objs) (void)hipGraphDestroy(g);
     if (h->cap) (void)hipStreamDestroy(h->cap);
