@@ -91,8 +91,9 @@ typedef struct {
 typedef struct jacobi_s jacobi_t;
 
 /* Bytes each grid buffer must hold for `d` (dims, layout and t are read).
- * AB: (nx+2)(ny+2)(nz+2) doubles.  COMPRESSED: the box plus t shift planes per
- * axis, (nx+2+t)(ny+2+t)(nz+2+t) doubles.  Errors: JACOBI_EINVAL. */
+ * AB: (nx+2)(ny+2)(nz+2) doubles.  COMPRESSED: the box plus 2t shift planes
+ * per axis, (nx+2+2t)(ny+2+2t)(nz+2+2t) doubles (2t, not t, so that a trip of
+ * any length <= t fits from every shift offset).  Errors: JACOBI_EINVAL. */
 int jacobi_grid_bytes(const jacobi_desc *d, size_t *bytes);
 
 /* Bytes of device workspace `d` needs (flags, reduction partials, and for

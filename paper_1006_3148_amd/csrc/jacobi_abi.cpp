@@ -113,7 +113,7 @@ struct jacobi_s {
     jacobi_desc d{};
     int t = 4;
     int64_t px = 0, py = 0;  // storage pitches of the FP64 grid(s)
-    int room = 0;            // compressed: shift room per axis
+    int room = 0;            // compressed: shift room per axis (2t)
     int off = 0;             // compressed: current origin offset per axis
     int cur = 0;             // AB: grid holding the current iterate
     hipStream_t stream = nullptr;
@@ -178,7 +178,7 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     if (d->inner_sweeps < 0) return fail(JACOBI_EINVAL, "inner_sweeps < 0");
     if (d->seg_len < 0) return fail(JACOBI_EINVAL, "seg_len < 0");
     const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
-    const int room = comp ? t : 0;
+    const int room = comp ? 2 * t : 0;
     const int64_t plane_bytes = (d->nx + 2 + room) * (d->ny + 2 + room) * 8;
     if (plane_bytes >= ((int64_t)1 << 31))
         return fail(JACOBI_EINVAL, "one k-plane must be < 2 GiB");
@@ -437,7 +437,10 @@ int jacobi_grid_bytes(const jacobi_desc* d, size_t* bytes)
     if (d->nx < 1 || d->ny < 1 || d->nz < 1)
         return fail(JACOBI_EINVAL, "interior dims must be >= 1");
     const int t = d->t == 0 ? 4 : d->t;
-    const int room = d->layout == JACOBI_LAYOUT_COMPRESSED ? t : 0;
+    // Compressed: 2t planes of shift room per axis, so that a trip of any
+    // length <= t fits in one direction from every offset (no split trips
+    // when sweep counts are not multiples of t).
+    const int room = d->layout == JACOBI_LAYOUT_COMPRESSED ? 2 * t : 0;
     *bytes = (size_t)((d->nx + 2 + room) * (d->ny + 2 + room) * (d->nz + 2 + room) * 8);
     return JACOBI_OK;
 }
@@ -484,7 +487,7 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     h->t = t;
     for (int T = 1; T <= t; ++T) h->plans[T] = plans[T];
     const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
-    h->room = comp ? t : 0;
+    h->room = comp ? 2 * t : 0;
     h->off = h->room;
     h->px = d->nx + 2 + h->room;
     h->py = h->px * (d->ny + 2 + h->room);

@@ -110,7 +110,7 @@ def test_sizes():
     d.layout = 1
     d.t = 3
     assert lib.jacobi_grid_bytes(ctypes.byref(d), ctypes.byref(n)) == 0
-    assert n.value == 15 * 11 * 9 * 8
+    assert n.value == 18 * 14 * 12 * 8   # box plus 2t shift planes per axis
     d.dtype = 1
     assert lib.jacobi_workspace_size(ctypes.byref(d), ctypes.byref(n)) == 0
     assert n.value >= 3 * 12 * 8 * 6 * 4
