@@ -223,3 +223,19 @@ def test_graph_replay_matches_eager_every_call():
     _assert_same(g.box(), oracle.sweeps_f64(box, total), "graph vs oracle")
     g.close()
     e.close()
+
+
+def test_solve_with_graph_replay_matches_eager():
+    """Run-to-tolerance on a handle that replays captured graphs: the same
+    sweep count and field as the eager handle and the oracle."""
+    from paper_1006_3148_amd import Jacobi
+    box = synth.sine_face_box(28, 21, 25, seed=8)
+    print("case solve with graphs 28x21x25", flush=True)
+    want, wdone, wrn, _ = oracle.solve_to_tol(box, 1e-8, check_every=48, max_sweeps=20000)
+    g = Jacobi(box, t=5, use_graph=True)
+    done, fin = g.solve(1e-8, 20000, 48)
+    got = g.box()
+    g.close()
+    assert done == wdone
+    _assert_same(got, want, "solve with graphs")
+    assert abs(fin - wrn) <= 1e-12 * wrn
