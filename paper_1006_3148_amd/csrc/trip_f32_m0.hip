@@ -1,0 +1,9 @@
+// Trip kernel instantiations: FP32, no right-hand side, mode 0.
+#include "trip_kernel.h"
+
+namespace jacobi_impl {
+hipError_t trip_dispatch_f32_m0(const TripConfig& c, const TripParams& p, hipStream_t s)
+{
+    return dispatch_unit<float, false, 0>(c, p, s);
+}
+}  // namespace jacobi_impl

@@ -1,0 +1,9 @@
+// Trip kernel instantiations: FP64, no right-hand side, mode 0.
+#include "trip_kernel.h"
+
+namespace jacobi_impl {
+hipError_t trip_dispatch_f64_m0(const TripConfig& c, const TripParams& p, hipStream_t s)
+{
+    return dispatch_unit<double, false, 0>(c, p, s);
+}
+}  // namespace jacobi_impl

@@ -1,0 +1,9 @@
+// Trip kernel instantiations: FP64, no right-hand side, mode 1.
+#include "trip_kernel.h"
+
+namespace jacobi_impl {
+hipError_t trip_dispatch_f64_m1(const TripConfig& c, const TripParams& p, hipStream_t s)
+{
+    return dispatch_unit<double, false, 1>(c, p, s);
+}
+}  // namespace jacobi_impl
