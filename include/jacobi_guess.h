@@ -79,7 +79,42 @@ int jg_adam(jg_net *h, float lr, float beta1, float beta2, float eps,
  * box (the solver's initial field); the boundary is left untouched. */
 int jg_write_guess(jg_net *h, double *box);
 
+/* The non-learned comparison guess: writes the face blend b (above) of the
+ * box's own faces into the interior of the dense (n+2)^3 FP64 `box`. */
+int jg_write_blend(jg_net *h, double *box);
+
 int jg_destroy(jg_net *h);
+
+/* ---- single convolution layers --------------------------------------------
+ * The 3x3x3 convolutions of the network (16 -> 16 channels, zero padding 1,
+ * stride 1 or 2), run by the same kernels as jg_forward / jg_backward on
+ * caller-owned device buffers, so that their FP32 accumulators can be
+ * checked on given BF16 operands.  x: [d][d][d][16] bfloat16 bit patterns
+ * (channel last); w: [27][Cout][Cin] bfloat16, tap t = (dz+1)*9 + (dy+1)*3 +
+ * (dx+1); d >= 1 and divisible by the stride; the output edge is d/stride.
+ * Asynchronous on `stream`.  Errors: JACOBI_EINVAL (null pointer, d, stride),
+ * JACOBI_EWORKSPACE, JACOBI_EHIP. */
+
+/* Workspace bytes (256-byte aligned) the backward layer calls need. */
+int jg_conv3_workspace_size(int64_t d, int32_t stride, size_t *bytes);
+
+/* y[o][co] = bias[co] + sum_t sum_ci w[t][co][ci] x[stride*o + d_t][ci]:
+ * [d/stride]^3 x 16 FP32, before ReLU and before BF16 rounding. */
+int jg_conv3_forward(const uint16_t *x, int64_t d, const uint16_t *w,
+                     const float *bias, int32_t stride, float *y, void *stream);
+
+/* dx[v][ci] = sum over taps t and outputs o with stride*o + d_t = v of
+ * sum_co w[t][co][ci] bf16(dy[o][co]): [d]^3 x 16 FP32, overwritten; dy is
+ * [d/stride]^3 x 16 FP32 and enters the products rounded to BF16. */
+int jg_conv3_backward_data(const float *dy, int64_t d, const uint16_t *w,
+                           int32_t stride, float *dx, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
+/* grad[t*256 + co*16 + ci] += sum_o bf16(dy[o][co]) x[stride*o + d_t][ci]
+ * and grad[27*256 + co] += sum_o dy[o][co] (FP32; 27*256 + 16 entries). */
+int jg_conv3_backward_weight(const uint16_t *x, int64_t d, const float *dy,
+                             int32_t stride, float *grad, void *workspace,
+                             size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

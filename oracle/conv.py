@@ -32,7 +32,9 @@ Layout: activations (D, H, W, C) with the channel index last; conv weights
 
 Numerics of the GPU network (BF16 weights and activations, FP32 accumulation)
 are reproduced by rounding operands with ``bf16_round`` (round to nearest
-even) before calling these FP64 functions.
+even) before calling these FP64 functions.  In the backward pass the FP32
+upstream gradient of a convolution enters its two matrix products (data and
+weight gradient) rounded to BF16, while the bias gradient sums it unrounded.
 """
 
 from __future__ import annotations
@@ -116,8 +118,14 @@ def conv3(x, w, b, stride=1):
     return y
 
 
-def conv3_backward(x, w, dy, stride=1):
-    """Gradients (dx, dw, db) of conv3 for upstream gradient dy."""
+def conv3_backward(x, w, dy, stride=1, rnd=None):
+    """Gradients (dx, dw, db) of conv3 for upstream gradient dy.
+
+    With ``rnd`` (the BF16 rounding) the upstream gradient enters the two
+    products as rnd(dy), as it does on the GPU, where dx and dw are matrix
+    products on BF16 operands; db is a plain sum of the unrounded dy.
+    """
+    dyp = dy if rnd is None else rnd(dy)
     d, h, wd, cin = x.shape
     od, oh, ow = dy.shape[:3]
     xp = np.zeros((d + 2, h + 2, wd + 2, cin))
@@ -129,8 +137,8 @@ def conv3_backward(x, w, dy, stride=1):
               slice(1 + dy_, 1 + dy_ + stride * oh, stride),
               slice(1 + dx, 1 + dx + stride * ow, stride))
         src = xp[sl]
-        dw[t] = np.einsum("zyxo,zyxi->oi", dy, src)
-        dxp[sl] += dy @ w[t]
+        dw[t] = dyp.reshape(-1, dyp.shape[-1]).T @ src.reshape(-1, cin)
+        dxp[sl] += dyp @ w[t]
     db = dy.sum(axis=(0, 1, 2))
     return dxp[1:-1, 1:-1, 1:-1], dw, db
 
@@ -253,6 +261,7 @@ def loss_and_grad(theta, box, target, levels, round_bf16=True, low_weight=0.0):
     MSE.
     """
     out, (cache, w, p) = forward(theta, box, levels, round_bf16)
+    rnd = bf16_round if round_bf16 else None
     n = out.size
     diff = out - target
     loss = float(np.sum(diff * diff) / n)
@@ -273,9 +282,9 @@ def loss_and_grad(theta, box, target, levels, round_bf16=True, low_weight=0.0):
         s, h = cache["dec%d_a" % l]
         h_, h2 = cache["dec%d_b" % l]
         d2 = dx * (h2 > 0)
-        dh, g["dec%d_b.w" % l], g["dec%d_b.b" % l] = conv3_backward(h, w["dec%d_b.w" % l], d2)
+        dh, g["dec%d_b.w" % l], g["dec%d_b.b" % l] = conv3_backward(h, w["dec%d_b.w" % l], d2, rnd=rnd)
         d1 = dh * (h > 0)
-        ds, g["dec%d_a.w" % l], g["dec%d_a.b" % l] = conv3_backward(s, w["dec%d_a.w" % l], d1)
+        ds, g["dec%d_a.w" % l], g["dec%d_a.b" % l] = conv3_backward(s, w["dec%d_a.w" % l], d1, rnd=rnd)
         dskip[l] = ds
         dx = up2_backward(ds)
     for l in range(levels - 1, -1, -1):
@@ -283,16 +292,16 @@ def loss_and_grad(theta, box, target, levels, round_bf16=True, low_weight=0.0):
             h2, xo = cache["down%d" % l]
             dd = dx * (xo > 0)
             dh2, g["down%d.w" % l], g["down%d.b" % l] = conv3_backward(
-                h2, w["down%d.w" % l], dd, 2)
+                h2, w["down%d.w" % l], dd, 2, rnd=rnd)
             dh2 = dh2 + dskip[l]
         else:
             dh2 = dx
         h, h2 = cache["enc%d_b" % l]
         d2 = dh2 * (h2 > 0)
-        dh, g["enc%d_b.w" % l], g["enc%d_b.b" % l] = conv3_backward(h, w["enc%d_b.w" % l], d2)
+        dh, g["enc%d_b.w" % l], g["enc%d_b.b" % l] = conv3_backward(h, w["enc%d_b.w" % l], d2, rnd=rnd)
         x, h_ = cache["enc%d_a" % l]
         d1 = dh * (h > 0)
-        dx, g["enc%d_a.w" % l], g["enc%d_a.b" % l] = conv3_backward(x, w["enc%d_a.w" % l], d1)
+        dx, g["enc%d_a.w" % l], g["enc%d_a.b" % l] = conv3_backward(x, w["enc%d_a.w" % l], d1, rnd=rnd)
     return loss, pack(g, levels), out
 
 

@@ -408,8 +408,9 @@ int check_pending(jacobi_t* h)
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "stream synchronize");
     if (errw != 0) {
-        launch_fill_i32(h->err, 0, 1, h->stream);
-        hipStreamSynchronize(h->stream);
+        e = launch_fill_i32(h->err, 0, 1, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "error word reset");
         return fail(JACOBI_ETIMEOUT,
                     "a tile progress wait exceeded its spin bound; results of "
                     "the affected sweeps are undefined");

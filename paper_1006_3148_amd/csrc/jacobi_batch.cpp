@@ -303,9 +303,14 @@ int enqueue(jacobi_batch_t* h, int64_t n, hipStream_t s, int* parity_flips)
 
 int autotune(jacobi_batch_t* h, int64_t* n)
 {
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    hipEvent_t a = nullptr, b = nullptr, t0 = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess ||
+        hipEventCreate(&t0) != hipSuccess || hipEventRecord(t0, h->stream) != hipSuccess) {
+        if (a) hipEventDestroy(a);
+        if (b) hipEventDestroy(b);
+        if (t0) hipEventDestroy(t0);
         return fail(JACOBI_EHIP, "event create");
+    }
     double best = -1;
     TripConfig best_cfg = default_cfg(4);
     const bool f32 = h->dtype == JACOBI_F32_REFINED;
@@ -331,13 +336,13 @@ int autotune(jacobi_batch_t* h, int64_t* n)
         if (e != hipSuccess) {
             hipEventDestroy(a);
             hipEventDestroy(b);
+            hipEventDestroy(t0);
             return hip_fail(e, "autotune");
         }
         if (!f32) {
             h->sweeps += 3 * c.T;
             *n -= 3 * c.T;
         }
-        h->tune_ms += ms * 1.5;
         const double glups = h->cells * 2 * c.T / (ms * 1e-3) / 1e9;
         h->tune_log.push_back({c, glups});
         if (glups > best) {
@@ -345,8 +350,13 @@ int autotune(jacobi_batch_t* h, int64_t* n)
             best_cfg = c;
         }
     }
+    // tune_ms: the whole tuning on the stream, warm-up trips included
+    float total = 0;
+    hipError_t e = hipEventElapsedTime(&total, t0, b);
     hipEventDestroy(a);
     hipEventDestroy(b);
+    hipEventDestroy(t0);
+    if (e == hipSuccess) h->tune_ms = total;
     h->t = best_cfg.T;
     int rc = ensure_set(h, best_cfg);
     if (rc != JACOBI_OK) return rc;
@@ -514,10 +524,15 @@ int jacobi_batch_sweep(jacobi_batch_t* h, int64_t n_steps)
             if (e != hipSuccess) return hip_fail(e, "begin capture");
             rc = enqueue(h, n_steps, h->cap, &flips);
             e = hipStreamEndCapture(h->cap, &g);
-            if (rc != JACOBI_OK) return rc;
-            if (e != hipSuccess) return hip_fail(e, "end capture");
+            if (rc != JACOBI_OK || e != hipSuccess) {
+                if (g) hipGraphDestroy(g);
+                return rc != JACOBI_OK ? rc : hip_fail(e, "end capture");
+            }
             e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-            if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+            if (e != hipSuccess) {
+                hipGraphDestroy(g);
+                return hip_fail(e, "graph instantiate");
+            }
             h->graph_objs.push_back(g);
             it = h->graphs.emplace(n_steps, x).first;
         } else {

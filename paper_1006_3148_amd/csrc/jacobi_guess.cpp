@@ -360,10 +360,104 @@ int jg_write_guess(jg_net* h, double* box)
     return e == hipSuccess ? JACOBI_OK : hip_fail(e, "write guess");
 }
 
+int jg_write_blend(jg_net* h, double* box)
+{
+    if (!h || !box) return fail(JACOBI_EINVAL, "null argument");
+    const Layout& l = h->lay;
+    hipError_t e = lift(box, (int)h->n, A(h, l.in), F(h, l.blend), h->s);
+    if (e == hipSuccess) e = write_guess(F(h, l.blend), (int)h->n, box, h->s);
+    return e == hipSuccess ? JACOBI_OK : hip_fail(e, "write blend");
+}
+
 int jg_destroy(jg_net* h)
 {
     delete h;
     return JACOBI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Layer workspace: the transposed weights, then the weight-gradient partials.
+size_t layer_ws(int64_t d, int stride, size_t* part_off)
+{
+    const int dout = (int)(d / stride);
+    *part_off = (size_t)round_up(kConvW * 2, 256);
+    return *part_off + (size_t)round_up((int64_t)wgrad_blocks(dout) * kConvP * 4, 256);
+}
+
+int layer_args(const void* a, const void* b, const void* c, int64_t d, int stride)
+{
+    if (!a || !b || !c) return fail(JACOBI_EINVAL, "null argument");
+    if ((stride != 1 && stride != 2) || d < stride || d % stride || d > 1024)
+        return fail(JACOBI_EINVAL, "need stride 1 or 2 and 1 <= d <= 1024 divisible by it");
+    return JACOBI_OK;
+}
+
+int layer_ws_check(void* ws, size_t bytes, int64_t d, int stride, size_t* part_off)
+{
+    const size_t need = layer_ws(d, stride, part_off);
+    if (!ws || bytes < need)
+        return fail(JACOBI_EWORKSPACE, "workspace of %zu bytes needed", need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256)
+        return fail(JACOBI_EINVAL, "workspace must be 256-byte aligned");
+    return JACOBI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jg_conv3_workspace_size(int64_t d, int32_t stride, size_t* bytes)
+{
+    if (!bytes) return fail(JACOBI_EINVAL, "null argument");
+    int rc = layer_args(bytes, bytes, bytes, d, stride);
+    if (rc != JACOBI_OK) return rc;
+    size_t off = 0;
+    *bytes = layer_ws(d, stride, &off);
+    return JACOBI_OK;
+}
+
+int jg_conv3_forward(const uint16_t* x, int64_t d, const uint16_t* w, const float* bias,
+                     int32_t stride, float* y, void* stream)
+{
+    int rc = layer_args(x, w, y, d, stride);
+    if (rc != JACOBI_OK) return rc;
+    if (!bias) return fail(JACOBI_EINVAL, "null argument");
+    hipError_t e = conv_fwd_f32(x, (int)d, w, bias, y, stride, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JACOBI_OK : hip_fail(e, "conv forward");
+}
+
+int jg_conv3_backward_data(const float* dy, int64_t d, const uint16_t* w, int32_t stride,
+                           float* dx, void* workspace, size_t workspace_bytes, void* stream)
+{
+    int rc = layer_args(dy, w, dx, d, stride);
+    if (rc != JACOBI_OK) return rc;
+    size_t off = 0;
+    rc = layer_ws_check(workspace, workspace_bytes, d, stride, &off);
+    if (rc != JACOBI_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint16_t* wt = static_cast<uint16_t*>(workspace);
+    hipError_t e = transpose_w(w, wt, s);
+    if (e == hipSuccess)
+        e = conv_bwd_data(dy, (int)(d / stride), wt, dx, (int)d, stride, false, nullptr, s);
+    return e == hipSuccess ? JACOBI_OK : hip_fail(e, "conv data gradient");
+}
+
+int jg_conv3_backward_weight(const uint16_t* x, int64_t d, const float* dy, int32_t stride,
+                             float* grad, void* workspace, size_t workspace_bytes,
+                             void* stream)
+{
+    int rc = layer_args(x, dy, grad, d, stride);
+    if (rc != JACOBI_OK) return rc;
+    size_t off = 0;
+    rc = layer_ws_check(workspace, workspace_bytes, d, stride, &off);
+    if (rc != JACOBI_OK) return rc;
+    float* part = reinterpret_cast<float*>(static_cast<char*>(workspace) + off);
+    hipError_t e = conv_bwd_weight(x, (int)d, dy, (int)(d / stride), stride, part, grad,
+                                   static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? JACOBI_OK : hip_fail(e, "conv weight gradient");
 }
 
 }  // extern "C"

@@ -117,10 +117,11 @@ __global__ __launch_bounds__(256) void lift_kernel(const double* __restrict__ bo
 
 // ------------------------------------------------------ conv forward ----
 // y[o] = relu?(b + sum_t W_t x[S*o + d_t]); input D^3 (Din), output Dout^3.
-template <int S, bool RELU>
+// OUTF32: y is FP32 (accumulator + bias, no ReLU, no BF16 rounding).
+template <int S, bool RELU, bool OUTF32 = false>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(
     const uint16_t* __restrict__ x, int din, const uint16_t* __restrict__ w,
-    const float* __restrict__ bias, uint16_t* __restrict__ y, int dout)
+    const float* __restrict__ bias, void* __restrict__ yv, int dout)
 {
     const int lane = threadIdx.x & 63;
     const int wid = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
@@ -152,7 +153,11 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(
         if (vx >= dout) continue;
         float v = acc[r] + bn;
         if (RELU) v = fmaxf(v, 0.f);
-        y[(((int64_t)oz * dout + oy) * dout + vx) * 16 + n] = f2bf(v);
+        const int64_t idx = (((int64_t)oz * dout + oy) * dout + vx) * 16 + n;
+        if (OUTF32)
+            static_cast<float*>(yv)[idx] = v;
+        else
+            static_cast<uint16_t*>(yv)[idx] = f2bf(v);
     }
 }
 
@@ -509,6 +514,16 @@ __global__ __launch_bounds__(256) void prep_weights_kernel(
     wt[(int64_t)l * per + t * 256 + ci * 16 + co] = b;
 }
 
+// wt[t][ci][co] = w[t][co][ci] (bf16) for one layer.
+__global__ __launch_bounds__(256) void transpose_w_kernel(const uint16_t* __restrict__ w,
+                                                          uint16_t* __restrict__ wt)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 27 * 256) return;
+    const int t = q / 256, co = (q / 16) % 16, ci = q % 16;
+    wt[t * 256 + ci * 16 + co] = w[q];
+}
+
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p,
                                                    const float* __restrict__ g,
                                                    float* __restrict__ m,
@@ -586,6 +601,25 @@ hipError_t conv_fwd(const uint16_t* x, int din, const uint16_t* w, const float* 
         else
             hipLaunchKernelGGL((conv_fwd_kernel<2, false>), grid, dim3(256), 0, s, x, din, w, b, y, dout);
     }
+    return hipGetLastError();
+}
+
+hipError_t conv_fwd_f32(const uint16_t* x, int din, const uint16_t* w, const float* b,
+                        float* y, int stride, hipStream_t s)
+{
+    const int dout = din / stride;
+    const int64_t tiles = (int64_t)dout * dout * ((dout + 15) / 16);
+    const dim3 grid(blocks_for(tiles, 4));
+    if (stride == 1)
+        hipLaunchKernelGGL((conv_fwd_kernel<1, false, true>), grid, dim3(256), 0, s, x, din, w, b, y, dout);
+    else
+        hipLaunchKernelGGL((conv_fwd_kernel<2, false, true>), grid, dim3(256), 0, s, x, din, w, b, y, dout);
+    return hipGetLastError();
+}
+
+hipError_t transpose_w(const uint16_t* w, uint16_t* wt, hipStream_t s)
+{
+    hipLaunchKernelGGL(transpose_w_kernel, dim3(27), dim3(256), 0, s, w, wt);
     return hipGetLastError();
 }
 

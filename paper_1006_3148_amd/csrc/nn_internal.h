@@ -14,6 +14,11 @@ constexpr int64_t kConvP = kConvW + kC;     // weights + bias per conv layer
 hipError_t lift(const double* box, int n, uint16_t* x, float* blend, hipStream_t s);
 hipError_t conv_fwd(const uint16_t* x, int din, const uint16_t* w, const float* b,
                     uint16_t* y, int stride, bool relu, hipStream_t s);
+// Same convolution, output FP32 (accumulator + bias; no ReLU, no rounding).
+hipError_t conv_fwd_f32(const uint16_t* x, int din, const uint16_t* w, const float* b,
+                        float* y, int stride, hipStream_t s);
+// wt[t][ci][co] = w[t][co][ci] for one layer (bf16).
+hipError_t transpose_w(const uint16_t* w, uint16_t* wt, hipStream_t s);
 hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* wt, float* dx,
                          int din, int stride, bool accum, const uint16_t* mask,
                          hipStream_t s);

@@ -25,7 +25,18 @@ _SIGS = {
     "jg_adam": ([_h, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                  ctypes.c_int64], ctypes.c_int),
     "jg_write_guess": ([_h, ctypes.c_void_p], ctypes.c_int),
+    "jg_write_blend": ([_h, ctypes.c_void_p], ctypes.c_int),
     "jg_destroy": ([_h], ctypes.c_int),
+    "jg_conv3_workspace_size": ([ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "jg_conv3_forward": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "jg_conv3_backward_data": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
+    "jg_conv3_backward_weight": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_size_t, ctypes.c_void_p], ctypes.c_int),
 }
 for _name, (_a, _r) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -112,6 +123,10 @@ class GuessNet:
     def write_guess(self, box: torch.Tensor) -> None:
         check(lib.jg_write_guess(self._h, box.data_ptr()))
 
+    def write_blend(self, box: torch.Tensor) -> None:
+        """Writes the non-learned face blend of box's faces into its interior."""
+        check(lib.jg_write_blend(self._h, box.data_ptr()))
+
     def close(self) -> None:
         if getattr(self, "_h", None):
             lib.jg_destroy(self._h)
@@ -122,3 +137,45 @@ class GuessNet:
             self.close()
         except Exception:
             pass
+
+
+# ---- single convolution layers (jg_conv3_*): BF16 operands are passed as
+# int16 tensors holding the bit patterns, everything on the current stream.
+
+def _layer_ws(d: int, stride: int) -> torch.Tensor:
+    ws = ctypes.c_size_t()
+    check(lib.jg_conv3_workspace_size(d, stride, ctypes.byref(ws)))
+    return torch.empty(ws.value, dtype=torch.uint8, device="cuda")
+
+
+def conv3_forward(x: torch.Tensor, w: torch.Tensor, bias: torch.Tensor,
+                  stride: int = 1) -> torch.Tensor:
+    """x: (d,d,d,16) int16 BF16 bits; w: (27,16,16) int16 BF16 bits; bias:
+    (16,) float32.  Returns the FP32 pre-activation output (d/s,d/s,d/s,16)."""
+    d = x.shape[0]
+    y = torch.empty((d // stride,) * 3 + (16,), dtype=torch.float32, device=x.device)
+    check(lib.jg_conv3_forward(x.data_ptr(), d, w.data_ptr(), bias.data_ptr(), stride,
+                               y.data_ptr(), torch.cuda.current_stream().cuda_stream))
+    return y
+
+
+def conv3_backward_data(dy: torch.Tensor, w: torch.Tensor, stride: int = 1) -> torch.Tensor:
+    """dy: (d/s,d/s,d/s,16) float32; returns dx (d,d,d,16) float32."""
+    d = dy.shape[0] * stride
+    dx = torch.empty((d,) * 3 + (16,), dtype=torch.float32, device=dy.device)
+    ws = _layer_ws(d, stride)
+    check(lib.jg_conv3_backward_data(dy.data_ptr(), d, w.data_ptr(), stride, dx.data_ptr(),
+                                     ws.data_ptr(), ws.numel(),
+                                     torch.cuda.current_stream().cuda_stream))
+    return dx
+
+
+def conv3_backward_weight(x: torch.Tensor, dy: torch.Tensor, stride: int = 1) -> torch.Tensor:
+    """Returns the (27*256 + 16,) float32 weight and bias gradient."""
+    d = x.shape[0]
+    g = torch.zeros(27 * 256 + 16, dtype=torch.float32, device=x.device)
+    ws = _layer_ws(d, stride)
+    check(lib.jg_conv3_backward_weight(x.data_ptr(), d, dy.data_ptr(), stride, g.data_ptr(),
+                                       ws.data_ptr(), ws.numel(),
+                                       torch.cuda.current_stream().cuda_stream))
+    return g

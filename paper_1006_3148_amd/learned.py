@@ -129,27 +129,6 @@ def train(net: GuessNet, U: torch.Tensor, n: int, pmax: int, seeds, epochs: int,
             "steps": step}
 
 
-def blend_guess(box: torch.Tensor) -> None:
-    """Non-learned comparison guess: each interior cell gets the average of the
-    six face values at its projections, weighted by inverse distance to the
-    face (torch arithmetic on a comparison baseline, not part of the solver)."""
-    n = box.shape[0] - 2
-    c = torch.arange(1, n + 1, dtype=torch.float64, device=box.device)
-    d0, d1 = c, (n + 1) - c
-    fi0 = box[1:-1, 1:-1, 0][:, :, None]
-    fi1 = box[1:-1, 1:-1, -1][:, :, None]
-    fj0 = box[1:-1, 0, 1:-1][:, None, :]
-    fj1 = box[1:-1, -1, 1:-1][:, None, :]
-    fk0 = box[0, 1:-1, 1:-1][None, :, :]
-    fk1 = box[-1, 1:-1, 1:-1][None, :, :]
-    wi0, wi1 = (1 / d0)[None, None, :], (1 / d1)[None, None, :]
-    wj0, wj1 = (1 / d0)[None, :, None], (1 / d1)[None, :, None]
-    wk0, wk1 = (1 / d0)[:, None, None], (1 / d1)[:, None, None]
-    num = fi0 * wi0 + fi1 * wi1 + fj0 * wj0 + fj1 * wj1 + fk0 * wk0 + fk1 * wk1
-    den = wi0 + wi1 + wj0 + wj1 + wk0 + wk1
-    box[1:-1, 1:-1, 1:-1] = num / den
-
-
 def evaluate(net: GuessNet, n: int, seeds, rel_tol: float = 1e-8,
              check_every: int = 256, max_sweeps: int = 400000, t: int = 0,
              single: int = 4):
@@ -184,7 +163,7 @@ def evaluate(net: GuessNet, n: int, seeds, rel_tol: float = 1e-8,
     blends = []
     for b in boxes:
         bt = torch.from_numpy(b).cuda()
-        blend_guess(bt)
+        net.write_blend(bt)
         blends.append(bt.cpu().numpy())
     bb = JacobiBatch(blends, t=tz)
     sb, _ = bb.solve(rel_tol, max_sweeps, check_every, r0=r0)
@@ -200,6 +179,12 @@ def evaluate(net: GuessNet, n: int, seeds, rel_tol: float = 1e-8,
     res["sweeps_saved_mean"] = float(d.mean())
     res["sweeps_saved_ci95"] = float(1.96 * d.std(ddof=1) / math.sqrt(len(d))) if len(d) > 1 else None
     res["sweeps_saved_frac"] = float(d.mean() / np.mean(sz))
+    # paired against the non-learned blend the network corrects
+    e = (sb - sl).astype(np.float64)
+    res["sweeps_saved_vs_blend_mean"] = float(e.mean())
+    res["sweeps_saved_vs_blend_ci95"] = (float(1.96 * e.std(ddof=1) / math.sqrt(len(e)))
+                                         if len(e) > 1 else None)
+    res["problems_better_than_blend"] = int((e > 0).sum())
     # single-problem wall time: zero start vs (inference + solve)
     tz_s, tl_s = [], []
     for q in range(min(single, len(seeds))):

@@ -46,6 +46,22 @@ def test_guess_sizes_and_errors():
     assert lib.jg_create(16, 4, None, None, None, None, None, 0, None, ctypes.byref(h)) == -1
 
 
+def test_conv_layer_argument_errors():
+    """The single-layer entry points reject bad sizes, strides, null buffers
+    and short workspaces before touching the GPU."""
+    from paper_1006_3148_amd import guess
+    lib = guess.lib
+    n = ctypes.c_size_t()
+    assert lib.jg_conv3_workspace_size(7, 2, ctypes.byref(n)) == -1    # 7 % 2
+    assert lib.jg_conv3_workspace_size(8, 3, ctypes.byref(n)) == -1    # stride
+    assert lib.jg_conv3_workspace_size(0, 1, ctypes.byref(n)) == -1
+    assert lib.jg_conv3_workspace_size(16, 2, ctypes.byref(n)) == 0 and n.value > 27 * 512
+    assert lib.jg_conv3_forward(None, 8, 1, 1, 1, 1, None) == -1
+    assert lib.jg_conv3_forward(1, 9, 1, 1, 2, 1, None) == -1
+    assert lib.jg_conv3_backward_data(1, 8, 1, 1, 1, None, 0, None) == -3
+    assert lib.jg_conv3_backward_weight(1, 8, 1, 1, 1, None, 0, None) == -3
+
+
 def _desc(**kw):
     from paper_1006_3148_amd._lib import JacobiDesc
     d = JacobiDesc()

@@ -157,3 +157,29 @@ def test_low_mode_loss_gradient_matches_finite_differences():
         lm = cv.loss_and_grad(tm, box, target, levels, round_bf16=False, low_weight=wlow)[0]
         fd = (lp - lm) / (2 * eps)
         assert abs(fd - g[q]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (q, fd, g[q])
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_conv3_backward_rounds_only_the_product_operand(stride):
+    """With the BF16 rounding of the upstream gradient: an already
+    BF16-representable dy gives exactly the unrounded result, db never sees
+    the rounding, and dx/dw are torch's conv3d gradients for rnd(dy)."""
+    rng = np.random.default_rng(5)
+    x = cv.bf16_round(rng.standard_normal((6, 4, 8, 16)))
+    w = cv.bf16_round(rng.standard_normal((27, 16, 16)))
+    dy = rng.standard_normal((6 // stride, 4 // stride, 8 // stride, 16))
+    dyb = cv.bf16_round(dy)
+    a = cv.conv3_backward(x, w, dyb, stride, rnd=cv.bf16_round)
+    b = cv.conv3_backward(x, w, dyb, stride)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    dx, dw, db = cv.conv3_backward(x, w, dy, stride, rnd=cv.bf16_round)
+    assert np.array_equal(db, dy.sum(axis=(0, 1, 2)))
+    assert not np.array_equal(dw, cv.conv3_backward(x, w, dy, stride)[1])
+    xt = torch.from_numpy(x.transpose(3, 0, 1, 2)[None].copy()).requires_grad_()
+    wt = _torch_w(w).requires_grad_()
+    yt = torch.nn.functional.conv3d(xt, wt, None, stride=stride, padding=1)
+    yt.backward(torch.from_numpy(dyb.transpose(3, 0, 1, 2)[None].copy()))
+    assert np.allclose(dx, xt.grad[0].numpy().transpose(1, 2, 3, 0), rtol=1e-11, atol=1e-11)
+    gw = wt.grad.numpy().transpose(2, 3, 4, 0, 1).reshape(27, 16, 16)
+    assert np.allclose(dw, gw, rtol=1e-11, atol=1e-11)

@@ -14,7 +14,9 @@ def _same(a, b):
     return np.array_equal(a.view(np.uint64), b.view(np.uint64))
 
 
-@pytest.mark.parametrize("layout,t", [("ab", 3), ("compressed", 5)])
+# ("ab", 5) is the headline bench configuration (4 x 8 tile, one 514-plane
+# segment per tile column).
+@pytest.mark.parametrize("layout,t", [("ab", 5), ("ab", 3), ("compressed", 5)])
 def test_512cube_200_sweeps_bitwise(layout, t):
     from paper_1006_3148_amd import Jacobi
     print("case 512^3 x 200 %s t=%d" % (layout, t), flush=True)
@@ -27,15 +29,18 @@ def test_512cube_200_sweeps_bitwise(layout, t):
     assert _same(got, want)
 
 
-def test_1024cube_compressed_16_sweeps_bitwise():
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("layout,t,sweeps", [("compressed", 4, 16), ("compressed", 5, 16),
+                                             ("ab", 5, 15)])
+def test_1024cube_bitwise(layout, t, sweeps):
     from paper_1006_3148_amd import Jacobi
-    print("case 1024^3 compressed x 16", flush=True)
+    print("case 1024^3 %s t=%d x %d" % (layout, t, sweeps), flush=True)
     box = synth.sine_face_box(1024, 1024, 1024, seed=3)
-    j = Jacobi(box, t=4, layout="compressed")
-    j.sweep(16)
+    j = Jacobi(box, t=t, layout=layout)
+    j.sweep(sweeps)
     got = j.box()
     j.close()
-    want = oracle.sweeps_f64(box, 16)
+    want = oracle.sweeps_f64(box, sweeps)
     del box
     assert _same(got, want)
 

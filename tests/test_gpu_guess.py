@@ -22,8 +22,63 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("n,levels", [(16, 3), (32, 4), (24, 2)])
-def test_forward_and_gradient_match_oracle(n, levels):
+def _bits(a):
+    """BF16 bit patterns (int16 tensor on the GPU) of BF16-representable values."""
+    import torch
+    u = np.asarray(a, np.float32).view(np.uint32) >> 16
+    return torch.from_numpy(u.astype(np.uint16).view(np.int16)).cuda()
+
+
+@pytest.mark.parametrize("d,stride", [(4, 1), (8, 1), (16, 1), (20, 1), (35, 1), (8, 2),
+                                      (16, 2), (20, 2), (128, 1), (128, 2)])
+def test_conv_layer_accumulators_match_oracle(d, stride):
+    """One convolution layer on identical BF16 operands: the FP32 accumulators
+    of the forward, data-gradient and weight-gradient kernels agree with the
+    FP64 oracle to 1e-4 relative L2; the bias gradient to 1e-5."""
+    import torch
+    from paper_1006_3148_amd import guess
+    print("case conv layer d=%d stride=%d" % (d, stride), flush=True)
+    rng = np.random.default_rng(100 + d + stride)
+    x = cv.bf16_round(np.maximum(rng.standard_normal((d, d, d, 16)), 0.0))
+    w = cv.bf16_round(rng.standard_normal((27, 16, 16)) * 0.1)
+    b = rng.standard_normal(16).astype(np.float32).astype(np.float64)
+    do = d // stride
+    dy = rng.standard_normal((do, do, do, 16)).astype(np.float32).astype(np.float64)
+    xg, wg = _bits(x), _bits(w)
+    y = guess.conv3_forward(xg, wg, torch.from_numpy(b.astype(np.float32)).cuda(), stride)
+    yref = cv.conv3(x, w, b, stride)
+    assert _rel(y.cpu().numpy().astype(np.float64), yref) < 1e-4
+    dyg = torch.from_numpy(dy.astype(np.float32)).cuda()
+    dx = guess.conv3_backward_data(dyg, wg, stride)
+    g = guess.conv3_backward_weight(xg, dyg, stride)
+    dxref, dwref, dbref = cv.conv3_backward(x, w, dy, stride, rnd=cv.bf16_round)
+    assert _rel(dx.cpu().numpy().astype(np.float64), dxref) < 1e-4
+    g = g.cpu().numpy().astype(np.float64)
+    assert _rel(g[:27 * 256], dwref.reshape(-1)) < 1e-4
+    assert _rel(g[27 * 256:], dbref) < 1e-5
+
+
+def _per_layer_rel(g, gref, levels):
+    out, o = {}, 0
+    for name, shp in cv.param_shapes(levels):
+        k = int(np.prod(shp))
+        if np.linalg.norm(gref[o:o + k]) > 0:
+            out[name] = _rel(g[o:o + k], gref[o:o + k])
+        o += k
+    return out
+
+
+# (n, levels, bound on the total gradient).  The whole network is not run on
+# identical operands: each side rounds its own activations to BF16 after
+# accumulating in its own order (FP32 MFMA, FP64 oracle), so about one
+# activation in a thousand differs by one BF16 step, and the differences
+# propagate.  With an 8^3 or larger bottom level the gradient then stays
+# within 1e-2; with the 4^3 bottom level of n=32, 4 levels (64 voxels, the
+# sums there are over few terms) it reaches 1.06e-2, and the bound is 2e-2.
+@pytest.mark.parametrize("n,levels,bound", [
+    (16, 3, 1e-2), (24, 2, 1e-2), (64, 4, 1e-2), (32, 4, 2e-2),
+    pytest.param(128, 4, 1e-2, marks=pytest.mark.timeout(900))])
+def test_forward_and_gradient_match_oracle(n, levels, bound):
     import torch
     from paper_1006_3148_amd import GuessNet
     print("case guess n=%d levels=%d" % (n, levels), flush=True)
@@ -42,16 +97,16 @@ def test_forward_and_gradient_match_oracle(n, levels):
     lref, gref, _ = cv.loss_and_grad(theta, box, target.astype(np.float64), levels,
                                      round_bf16=True)
     assert abs(loss - lref) <= 1e-3 * abs(lref)
-    assert _rel(g, gref) < 3e-2, _rel(g, gref)
-    # every layer's gradient points the same way
-    o = 0
-    for name, shp in cv.param_shapes(levels):
-        k = int(np.prod(shp))
-        a, b = g[o:o + k], gref[o:o + k]
-        o += k
-        if np.linalg.norm(b) > 1e-12:
-            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
-            assert cos > 0.995, (name, cos)
+    # post-BF16 gradients, relative L2: the whole vector within `bound`; with a
+    # bottom level of 8^3 or more also every layer within 3 bound (at 4^3 a
+    # bias gradient sums 64 ReLU-masked terms, and one mask that flips with
+    # an activation's rounding moves it by several percent)
+    per = _per_layer_rel(g, gref, levels)
+    worst = max(per, key=per.get)
+    print("worst layer %s %.2e, total %.2e" % (worst, per[worst], _rel(g, gref)), flush=True)
+    assert _rel(g, gref) < bound, _rel(g, gref)
+    if n >> (levels - 1) >= 8:
+        assert per[worst] < 3 * bound, (worst, per[worst])
     net.close()
 
 
@@ -81,7 +136,7 @@ def test_low_mode_loss_matches_oracle(weight):
         lref, gref, _ = cv.loss_and_grad(theta, box, target.astype(np.float64), levels,
                                          round_bf16=True, low_weight=w)
         assert abs(loss - lref) <= 2e-3 * abs(lref), (w, loss, lref)
-        assert _rel(g, gref) < 3e-2, (w, _rel(g, gref))
+        assert _rel(g, gref) < 1e-2, (w, _rel(g, gref))
     net.close()
 
 
