@@ -81,6 +81,16 @@ typedef struct {
                             per (n_steps, current grid) into a hipGraph on an
                             internal stream (up to 8 kept) and replayed on
                             `stream`; 0: every trip is launched eagerly */
+    int32_t teams;       /* A/B FP64: 0 or 1 = one launch per trip (kernel
+                            boundaries are the only synchronization); k >= 2
+                            = up to k trips ("teams", Sect. 2.1) in one
+                            persistent launch, tiles synchronized by per-tile
+                            progress counters (Sect. 2.2, Eq. (3)); 1..1024 */
+    int32_t looseness;   /* with teams >= 2, the upper looseness d_u of
+                            Eq. (3): a tile starts trip r only once every
+                            tile has finished trip r-d_u-1 (0 = lockstep, a
+                            barrier between trips inside the launch); < 0 =
+                            no such bound (neighbour counters only) */
     void *grid0;         /* FP64 grid buffer (device); see jacobi_grid_bytes */
     void *grid1;         /* second FP64 grid for JACOBI_LAYOUT_AB, else NULL */
     void *workspace;     /* device scratch owned by the caller */

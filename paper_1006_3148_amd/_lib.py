@@ -51,6 +51,7 @@ class JacobiDesc(ctypes.Structure):
         ("t", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("rows_per_wave", ctypes.c_int32), ("seg_len", ctypes.c_int32),
         ("inner_sweeps", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+        ("teams", ctypes.c_int32), ("looseness", ctypes.c_int32),
         ("grid0", ctypes.c_void_p), ("grid1", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),

@@ -34,7 +34,8 @@ struct TripParams {
     int tiles_x, tiles_y, segs, seg_len;
     int ntiles;
     int mode;          // 0: blockIdx tiles (A/B); 1: tickets + flags
-                       // (compressed); 2: batch table, tickets
+                       // (compressed); 2: batch table, tickets; 3: several
+                       // trips (teams) in one persistent launch (A/B)
     int dir;           // +1 forward shift (-t), -1 backward shift (+t); mode 1
     int* flags;        // per-tile progress words, stride kFlagStride ints
     int* ticket;       // ticket counter (zeroed before the launch)
@@ -44,6 +45,11 @@ struct TripParams {
     int count;                  // mode 2: number of problems
     const int* parity;          // mode 2: A/B parity word (device memory)
     int rhs_in_table;           // mode 2: FP32 rhs pointers are in the table
+    int teams;                  // mode 3: trips in the launch (team r reads
+                                // src for even r, dst for odd r)
+    int looseness;              // mode 3: d_u (< 0: no bound)
+    int* done;                  // mode 3: per-team count of finished tiles,
+                                // stride kFlagStride ints (zeroed)
 };
 
 constexpr int kFlagStride = 32;  // ints per flag (128 B line each)

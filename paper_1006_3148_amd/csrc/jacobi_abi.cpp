@@ -133,6 +133,7 @@ struct jacobi_s {
     double* partials = nullptr;
     int* flags = nullptr;
     int64_t flag_ints = 0;
+    int* done = nullptr;     // per-team finished-tile counts (teams >= 2)
     float* e[2] = {nullptr, nullptr};
     float* rhs = nullptr;
     AuxProblem aux{};         // residual / refinement view of this problem
@@ -156,9 +157,11 @@ struct jacobi_s {
 namespace {
 
 struct Layout {
-    size_t partials_off, flags_off, e0_off, e1_off, rhs_off, total;
+    size_t partials_off, flags_off, done_off, e0_off, e1_off, rhs_off, total;
     int64_t flag_ints;
 };
+
+constexpr int kMaxTeams = 1024;
 
 int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                       Layout* lay)
@@ -178,6 +181,11 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
         return fail(JACOBI_EUNSUPPORTED,
                     "sweeps per trip t=%d not supported (1..8)", t);
     if (d->inner_sweeps < 0) return fail(JACOBI_EINVAL, "inner_sweeps < 0");
+    if (d->teams < 0 || d->teams > kMaxTeams)
+        return fail(JACOBI_EINVAL, "teams must be in 0..%d", kMaxTeams);
+    if (d->teams > 1 && (d->layout != JACOBI_LAYOUT_AB || d->dtype != JACOBI_F64))
+        return fail(JACOBI_EUNSUPPORTED,
+                    "several trips per launch (teams >= 2) need the AB layout and FP64");
     if (d->seg_len < 0) return fail(JACOBI_EINVAL, "seg_len < 0");
     const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
     const int room = comp ? 2 * t : 0;
@@ -215,8 +223,10 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     const int nb = residual_plan(&ap);
     L.partials_off = 256;
     L.flags_off = (size_t)round_up(L.partials_off + 2 * (int64_t)nb * sizeof(double), 256);
-    L.flag_ints = comp ? max_tiles * kFlagStride : 0;
-    size_t end = (size_t)round_up(L.flags_off + L.flag_ints * sizeof(int), 256);
+    const bool teams = d->teams > 1;
+    L.flag_ints = (comp || teams) ? max_tiles * kFlagStride : 0;
+    L.done_off = (size_t)round_up(L.flags_off + L.flag_ints * sizeof(int), 256);
+    size_t end = L.done_off + (teams ? (size_t)d->teams * kFlagStride * sizeof(int) : 0);
     L.e0_off = L.e1_off = L.rhs_off = 0;
     if (d->dtype == JACOBI_F32_REFINED) {
         const int64_t box = (d->nx + 2) * (d->ny + 2) * (d->nz + 2);
@@ -233,7 +243,7 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
 
 hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
                        const float* rhs, int64_t px, int64_t py, int mode,
-                       int dir)
+                       int dir, int teams = 1)
 {
     const Plan& pl = h->plans[T];
     TripParams p{};
@@ -258,11 +268,15 @@ hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
     p.ticket = h->ticket;
     p.err = h->err;
     p.spin_limit = h->spin_limit;
-    if (mode == 1) {
+    p.teams = teams;
+    p.looseness = h->d.looseness;
+    p.done = h->done;
+    if (mode == 1 || mode == 3) {
         hipError_t e = launch_fill_i32(h->flags, 0, (int64_t)pl.ntiles * kFlagStride,
                                        h->run);
-        if (e != hipSuccess) return e;
-        e = launch_fill_i32(h->ticket, 0, 1, h->run);
+        if (e == hipSuccess && mode == 3)
+            e = launch_fill_i32(h->done, 0, (int64_t)teams * kFlagStride, h->run);
+        if (e == hipSuccess) e = launch_fill_i32(h->ticket, 0, 1, h->run);
         if (e != hipSuccess) return e;
     }
     return f32 ? launch_trip_f32(pl.cfg, p, h->run)
@@ -289,7 +303,14 @@ int run_f64(jacobi_t* h, int64_t n)
     while (n > 0) {
         int L = (int)std::min<int64_t>(h->t, n);
         hipError_t e;
-        if (h->d.layout == JACOBI_LAYOUT_AB) {
+        if (h->d.layout == JACOBI_LAYOUT_AB && h->d.teams > 1 && n >= 2 * (int64_t)h->t) {
+            // several full trips in one persistent launch
+            const int k = (int)std::min<int64_t>(n / h->t, h->d.teams);
+            L = k * h->t;
+            e = launch_trip(h, h->t, false, grid_origin(h, h->cur),
+                            grid_origin(h, 1 - h->cur), nullptr, h->px, h->py, 3, 1, k);
+            h->cur ^= (k & 1);
+        } else if (h->d.layout == JACOBI_LAYOUT_AB) {
             e = launch_trip(h, L, false, grid_origin(h, h->cur),
                             grid_origin(h, 1 - h->cur), nullptr, h->px, h->py,
                             0, 1);
@@ -509,6 +530,7 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     h->partials = reinterpret_cast<double*>(h->ws + L.partials_off);
     h->flags = reinterpret_cast<int*>(h->ws + L.flags_off);
     h->flag_ints = L.flag_ints;
+    h->done = reinterpret_cast<int*>(h->ws + L.done_off);
     if (d->dtype == JACOBI_F32_REFINED) {
         h->e[0] = reinterpret_cast<float*>(h->ws + L.e0_off);
         h->e[1] = reinterpret_cast<float*>(h->ws + L.e1_off);

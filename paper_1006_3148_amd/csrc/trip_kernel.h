@@ -407,12 +407,75 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     }
 }
 
+// Teams (MODE 3): team r applies trip r of the launch.  Before tile `tile`
+// of team r starts, the tiles whose outputs its input region reads (its
+// neighbours within one tile in i, j and k, itself included) must have
+// finished team r-1 -- the safety half of Eq. (3), on per-tile counters of
+// completed teams -- and, with looseness d_u >= 0, every tile must have
+// finished team r-d_u-1 (a team runs at most d_u trips ahead of the slowest
+// tile; d_u = 0 is lockstep, a barrier between trips inside the kernel).
+// Every wave waits itself and then acquires at agent scope, so the planes
+// other workgroups wrote (possibly on another XCD) are read from memory.
+// The bounded spin raises the error word instead of hanging.
+__device__ __attribute__((noinline)) void wait_team(const int* flags, const int* done,
+                                                    int* err, int tiles_x, int tiles_y,
+                                                    int segs, int ntiles, int looseness,
+                                                    long long spin_limit, int tile, int team)
+{
+    const int lane = threadIdx.x & 63;
+    const int tx = tile % tiles_x;
+    const int ty = (tile / tiles_x) % tiles_y;
+    const int sg = tile / (tiles_x * tiles_y);
+    const int* word = nullptr;
+    int need = 0;
+    if (lane < 27) {
+        const int nx = tx + lane % 3 - 1, ny = ty + (lane / 3) % 3 - 1,
+                  ns = sg + lane / 9 - 1;
+        if (nx >= 0 && nx < tiles_x && ny >= 0 && ny < tiles_y && ns >= 0 && ns < segs) {
+            word = flags + (int64_t)((ns * tiles_y + ny) * tiles_x + nx) * kFlagStride;
+            need = team;
+        }
+    } else if (lane == 27 && looseness >= 0 && team - looseness - 1 >= 0) {
+        word = done + (int64_t)(team - looseness - 1) * kFlagStride;
+        need = ntiles;
+    }
+    int64_t spins = 0;
+    for (;;) {
+        const bool ok = !word || flag_load(word) >= need;
+        if (__all(ok)) break;
+        if (++spins > spin_limit || flag_load(err) != 0) {
+            if (lane == 0) atomicCAS(err, 0, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Publishes "tile finished team": every wave releases its stores at agent
+// scope, then one thread raises the tile's counter and the team's count.
+__device__ __forceinline__ void finish_team(const TripParams& p, int tile, int team)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        flag_store(p.flags + (int64_t)tile * kFlagStride, team + 1);
+        __hip_atomic_fetch_add(p.done + (int64_t)team * kFlagStride, 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // MODE 0: one problem, tile = f(blockIdx) (A/B; kernel boundary between
 //         trips is the only synchronization).
 // MODE 1: one problem, tiles from a ticket counter, progress flags
 //         (compressed single grid).
 // MODE 2: a batch of independent problems described by p.table; tiles of all
 //         problems from one ticket counter; A/B parity read from *p.parity.
+// MODE 3: one problem, p.teams trips in one persistent launch (A/B): work
+//         items (team, tile) from one ticket counter in team-major order,
+//         so every item an item waits for has a smaller ticket (no
+//         deadlock, whatever number of workgroups is resident).
 template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE>
 __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 {
@@ -425,6 +488,7 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 
     for (int iter = 0;; ++iter) {
         int tile;
+        int team = 0;
         if (MODE == 0) {
             if (iter > 0) return;
             tile = xcd_tile(blockIdx.x, p.ntiles);
@@ -433,8 +497,14 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             if (threadIdx.x == 0) tile_sh = atomicAdd(p.ticket, 1);
             __syncthreads();
             const int t = tile_sh;
-            if (t >= p.ntiles) return;
-            tile = (MODE == 1 && p.dir < 0) ? p.ntiles - 1 - t : t;
+            if (MODE == 3) {
+                if (t >= p.ntiles * p.teams) return;
+                team = t / p.ntiles;
+                tile = t - team * p.ntiles;
+            } else {
+                if (t >= p.ntiles) return;
+                tile = (MODE == 1 && p.dir < 0) ? p.ntiles - 1 - t : t;
+            }
         }
         Geo g;
         if (MODE == 2) {
@@ -462,8 +532,10 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             g.seg_len = bp.seg_len;
             tile -= bp.tile_base;
         } else {
-            g.src = p.src;
-            g.dst = p.dst;
+            // MODE 3: odd teams read the grid even teams write
+            const bool swap = MODE == 3 && (team & 1);
+            g.src = swap ? p.dst : p.src;
+            g.dst = swap ? const_cast<void*>(p.src) : p.dst;
             g.rhs = p.rhs;
             g.px = p.px;
             g.py = p.py;
@@ -482,10 +554,14 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
         const int ilo = tx * OX - T, jlo = ty * OY - T;
         const bool interior_tile = ilo >= 1 && ilo + 63 <= g.nx && jlo >= 1 &&
                                    jlo + H - 1 <= g.ny;
+        if (MODE == 3 && team > 0)
+            wait_team(p.flags, p.done, p.err, p.tiles_x, p.tiles_y, p.segs, p.ntiles,
+                      p.looseness, p.spin_limit, tile, team);
         if (interior_tile)
             run_tile<Real, T, R, W, PF, RHS, FLAGS, false>(p, g, tile, xch);
         else
             run_tile<Real, T, R, W, PF, RHS, FLAGS, true>(p, g, tile, xch);
+        if (MODE == 3) finish_team(p, tile, team);
     }
 }
 
@@ -510,7 +586,8 @@ hipError_t launch_mode(const TripParams& p, hipStream_t s)
             64 * W, 0);
     if (e != hipSuccess) return e;
     int grid = cus * (per_cu > 0 ? per_cu : 1);
-    if (grid > p.ntiles) grid = p.ntiles;
+    const int64_t items = MODE == 3 ? (int64_t)p.ntiles * p.teams : p.ntiles;
+    if (grid > items) grid = (int)items;
     hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE>), dim3(grid), block,
                        0, s, p);
     return hipGetLastError();

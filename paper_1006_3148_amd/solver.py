@@ -45,7 +45,8 @@ class Jacobi:
     def __init__(self, box, t: int = 4, layout: str = "ab", dtype: str = "f64",
                  inner_sweeps: int = 0, tile_rows: int = 0,
                  rows_per_wave: int = 0, seg_len: int = 0, stream=None,
-                 device: str = "cuda", use_graph: bool = False):
+                 device: str = "cuda", use_graph: bool = False, teams: int = 0,
+                 looseness: int = -1):
         if isinstance(box, np.ndarray):
             box_t = torch.from_numpy(np.ascontiguousarray(box, dtype=np.float64))
         else:
@@ -65,6 +66,8 @@ class Jacobi:
         d.seg_len = seg_len
         d.inner_sweeps = inner_sweeps
         d.use_graph = 1 if use_graph else 0
+        d.teams = teams
+        d.looseness = looseness
         self.layout = layout
         gb = ctypes.c_size_t()
         check(lib.jacobi_grid_bytes(ctypes.byref(d), ctypes.byref(gb)))
