@@ -24,7 +24,7 @@
  *
  * Memory: every device buffer is owned by the caller (e.g. allocated with
  * PyTorch); the library allocates no device memory and owns only the host
- * handle.  Box layout: element (i,j,k) of a frame with origin O and strides
+ * handle (and the static reduction array of jacobi_residual_noalloc).  Box layout: element (i,j,k) of a frame with origin O and strides
  * (1, px, py) is O[k*py + j*px + i]; i is contiguous.
  *
  * Errors: every function returns 0 (JACOBI_OK) or a negative jacobi_status and
@@ -220,6 +220,27 @@ int jacobi_batch_tune_log(jacobi_batch_t *h, int32_t cap, int32_t *t,
                           double *glups, int32_t *n);
 int jacobi_batch_sync(jacobi_batch_t *h);
 int jacobi_batch_destroy(jacobi_batch_t *h);
+
+/* ---- no-allocation residual ----------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual of jacobi_residual, ||fold(u nbrs) - 6u||_2 and max |r| over the
+ * interior of the FP64 field whose logical cell (0,0,0) is at `origin`
+ * (strides {1, px, py} elements; boundary layer included, so px >= nx+2,
+ * py >= px*(ny+2)), written to the device array out[0] (norm), out[1]
+ * (max |r|).  No handle, no workspace, no allocation: the reduction partials
+ * live in a static device array of the library, JACOBI_NOALLOC_SCRATCH_BYTES
+ * per GPU, held until the process ends; the field may need up to
+ * JACOBI_NOALLOC_SCRATCH_BYTES / 16 reduction blocks, i.e.
+ * ceil(nx/64) * ceil(ny/4) <= 65536 (larger fields: JACOBI_EINVAL).
+ * Asynchronous on `stream`; the result is bitwise that of jacobi_residual.
+ * All calls on one GPU share its array: calls that overlap on one GPU
+ * (different streams or threads) race; calls on one stream are ordered.
+ * Errors: JACOBI_EINVAL, JACOBI_EHIP. */
+#define JACOBI_NOALLOC_SCRATCH_BYTES (1 << 20)
+int jacobi_residual_noalloc(const double *origin, int64_t px, int64_t py,
+                            int64_t nx, int64_t ny, int64_t nz, double *out,
+                            void *stream);
 
 /* ---- bandwidth probes (Table 1 of the paper: STREAM copy and the
  *      array-update loop a[i] += 1 of Sect. 2.3) ---------------------------

@@ -107,6 +107,9 @@ _SIGS = {
                               ctypes.c_int),
     "jacobi_batch_sync": ([_h], ctypes.c_int),
     "jacobi_batch_destroy": ([_h], ctypes.c_int),
+    "jacobi_residual_noalloc": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "jacobi_probe_copy": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                            ctypes.c_void_p], ctypes.c_int),
     "jacobi_probe_update": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p],

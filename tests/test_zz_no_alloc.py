@@ -1,0 +1,60 @@
+"""jacobi_residual_noalloc (static scratch, no handle, no workspace) against
+jacobi_residual on the same fields: two calls in a row, the second on a
+smaller field with another layout, each bitwise equal to the handle's result
+and within 1e-12 of the oracle's norm."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _noalloc(j):
+    import torch
+    from paper_1006_3148_amd import lib
+    from paper_1006_3148_amd._lib import check
+    origin = ctypes.c_void_p()
+    strides = (ctypes.c_int64 * 3)()
+    check(lib.jacobi_current(j._h, ctypes.byref(origin), strides))
+    out = torch.full((2,), -1.0, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    j.sync()
+    check(lib.jacobi_residual_noalloc(origin.value, strides[1], strides[2], j.nx, j.ny,
+                                      j.nz, out.data_ptr(), stream.cuda_stream))
+    stream.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("first,second", [
+    ((70, 45, 37, "ab", 9), (13, 9, 5, "compressed", 7)),
+])
+def test_noalloc_residual_matches_handle(first, second):
+    from paper_1006_3148_amd import Jacobi
+    import torch
+    for nx, ny, nz, layout, sweeps in (first, second):
+        print("case noalloc residual %dx%dx%d %s" % (nx, ny, nz, layout), flush=True)
+        box = synth.uniform_box(nx, ny, nz, seed=nx + ny)
+        j = Jacobi(box, t=3, layout=layout, stream=torch.cuda.current_stream())
+        j.sweep(sweeps)
+        got = _noalloc(j)
+        l2, mx = j.residual()
+        field = j.box()
+        j.close()
+        assert got[0] == l2 and got[1] == mx, (got, l2, mx)
+        want = oracle.residual_norm(field)
+        assert abs(got[0] - want) <= 1e-12 * want, (got[0], want)
+        assert got[1] == np.max(np.abs(oracle.residual_f64(field)))
+
+
+def test_noalloc_rejects_fields_beyond_the_scratch():
+    from paper_1006_3148_amd import lib
+    # ceil(65536/64) * ceil(2048/4) = 524288 blocks > 65536
+    nx, ny = 65536, 2048
+    rc = lib.jacobi_residual_noalloc(256, nx + 2, (nx + 2) * (ny + 2), nx, ny, 4, 256, None)
+    assert rc == -1
+    assert b"static scratch" in lib.jacobi_last_error()
