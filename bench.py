@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--tts-only", type=int, default=0, metavar="N",
                     help="only measure time to 1e-8 at N^3 and print it as JSON")
+    ap.add_argument("--tts-budget", type=float, default=0.0, metavar="S",
+                    help="with --tts-only: seconds per form before extrapolating")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--quick", action="store_true",
@@ -92,24 +94,42 @@ def time_steps(j, steps, sweeps, t, torch):
     return wall, gpu_ms, trip_ms, len(full)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, seconds):
-    import numpy as np
+    """The plain C oracle on the host cores: all OpenMP threads (the reported
+    value) and one thread, each on a bounded number of sweeps of the same
+    512^3 box (about seconds/2 of CPU time each)."""
     import oracle
     import synth
     box = synth.uniform_box(n, n, n, seed=2)
+    out = {}
+    for nt in (oracle.max_threads(), 1):
+        t0 = time.perf_counter()
+        oracle.sweeps_f64(box, 1, nthreads=nt)
+        one = time.perf_counter() - t0
+        s = max(1, int(0.5 * seconds / max(one, 1e-3)))
+        t0 = time.perf_counter()
+        oracle.sweeps_f64(box, s, nthreads=nt)
+        dt = time.perf_counter() - t0
+        out[nt] = (s, dt, n ** 3 * s / dt / 1e9)
     nt = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.sweeps_f64(box, 1, nthreads=nt)
-    one = time.perf_counter() - t0
-    s = max(1, int(seconds / max(one, 1e-3)))
-    t0 = time.perf_counter()
-    oracle.sweeps_f64(box, s, nthreads=nt)
-    dt = time.perf_counter() - t0
-    del np
-    return {"value": round(n ** 3 * s / dt / 1e9, 4), "unit": "GLUP/s",
-            "cores": nt, "kind": "oracle",
-            "sample": "%d^3 interior, %d FP64 sweeps of the plain C oracle "
-                      "(OpenMP over k planes, %d threads), %.1f s" % (n, s, nt, dt)}
+    s, dt, g = out[nt]
+    s1, dt1, g1 = out[1]
+    return {"value": round(g, 4), "unit": "GLUP/s", "cores": nt, "kind": "oracle",
+            "single_thread": round(g1, 4), "cpu_model": _cpu_model(),
+            "nproc": os.cpu_count(),
+            "sample": "%d^3 interior, plain C oracle (OpenMP over k planes): %d FP64 "
+                      "sweeps on %d threads in %.1f s; %d sweeps on 1 thread in %.1f s"
+                      % (n, s, nt, dt, s1, dt1)}
 
 
 def glups(n, sweeps, seconds):
@@ -180,7 +200,8 @@ def main():
                           "bytes_written": b.numel() * 8, "launches": 5}))
         return
     if args.tts_only:
-        res = bench_time_to_tol(torch, args.tts_only, args.t or DEFAULT_T)
+        res = bench_time_to_tol(torch, args.tts_only, args.t or DEFAULT_T,
+                                budget=args.tts_budget, layout=args.layout or "ab")
         print(json.dumps({"time_to_1e-8": res}), flush=True)
         return
     n, sweeps = args.n, args.sweeps
@@ -361,34 +382,148 @@ def bench_small_64(torch, sweeps=100, reps=5):
     return res
 
 
-def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024):
+def _closed_form(torch, n, modes):
+    """Exact solution of the discrete Laplace problem for sine-mode faces on
+    the GPU (float64): one separable term per face mode,
+    sin(th_a a) sin(th_b b) sinh(beta d) / sinh(beta (n+1)) with
+    cosh(beta) = 3 - cos(th_a) - cos(th_b) and d the distance from the
+    opposite face; faces i0, i1, j0, j1, k0, k1, in-plane axes in (i, j, k)
+    order (the first carries p)."""
+    import math
+    idx = torch.arange(n + 2, dtype=torch.float64, device="cuda")
+    u = torch.zeros((n + 2,) * 3, dtype=torch.float64, device="cuda")
+    # axis index in the (k, j, i) tensor: i -> 2, j -> 1, k -> 0
+    specs = [(2, 1, 0, False), (2, 1, 0, True), (1, 2, 0, False), (1, 2, 0, True),
+             (0, 2, 1, False), (0, 2, 1, True)]
+    for face, (ax_n, ax_a, ax_b, far) in zip(modes, specs):
+        for p, q, amp in face:
+            ta, tb = math.pi * p / (n + 1), math.pi * q / (n + 1)
+            beta = math.acosh(3.0 - math.cos(ta) - math.cos(tb))
+            d = idx if far else (n + 1) - idx
+            prof = torch.sinh(beta * d) / math.sinh(beta * (n + 1))
+            shape = [1, 1, 1]
+            va, vb = torch.sin(ta * idx), torch.sin(tb * idx)
+            sa, sb, sn = list(shape), list(shape), list(shape)
+            sa[ax_a] = n + 2
+            sb[ax_b] = n + 2
+            sn[ax_n] = n + 2
+            u += amp * va.view(sa) * vb.view(sb) * prof.view(sn)
+    return u
+
+
+def _field_errors(torch, u, ref):
+    """max |u - ref| and ||u - ref||_2 / ||ref||_2 over the interior."""
+    d = (u[1:-1, 1:-1, 1:-1] - ref[1:-1, 1:-1, 1:-1])
+    r = ref[1:-1, 1:-1, 1:-1]
+    return {"max_abs": float(d.abs().max()),
+            "rel_l2": float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(r))}
+
+
+def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024, budget=0.0, layout="ab"):
     """Sweeps and seconds to ||r|| <= 1e-8 ||r0|| from the zero start with
-    sine-mode faces: FP64 blocked (t), FP32-refined, plain FP64 t=1.  Each
-    solve runs in calls of 64 checks (r0 held fixed), printing progress."""
+    sine-mode faces (seed 3): FP64 blocked (t), FP32-refined (FP32 sweeps of
+    the correction equation, FP64 residual and update) and plain FP64 single
+    sweeps (t=1).
+
+    Each solve runs in calls of 16 checks with r0 fixed, printing progress.
+    With budget > 0 (seconds) a form stops when its budget is spent; the rest
+    of the way to the tolerance is then extrapolated at the decay rate of the
+    residual over the last 16 checks and at the form's measured GLUP/s (and
+    labelled so).  The FP32-refined run stops at the FP64 run's sweep count,
+    so that the two fields are compared at equal sweeps; the single-sweep
+    form is timed on the first 8 checks only and extrapolated to the FP64
+    count (its iterates are bitwise those of the blocked form).  The FP32 and
+    FP64 fields are compared with each other and with the closed-form
+    solution, next to the residual bound ||r||/(6 (1 - mu1)) on ||u - u*||."""
+    import math
     import synth
     from paper_1006_3148_amd import Jacobi
-    box = synth.sine_face_box(n, n, n, seed=3)
-    res = {"n": n, "rel_tol": rel_tol, "check_every": check}
+    modes = synth.sine_face_modes(3)
+    box = torch.from_numpy(synth.sine_face_box(n, n, n, seed=3)).cuda()
+    mu1 = math.cos(math.pi / (n + 1))
+    res = {"n": n, "rel_tol": rel_tol, "check_every": check, "layout": layout, "t": t,
+           "budget_s": budget, "slowest_mode_factor": mu1}
+    fields = {}
+    r0 = None
+    target_sweeps = None
     for name, kw in (("f64_blocked", dict(t=t)),
                      ("f32_refined", dict(t=t, dtype="f32_refined", inner_sweeps=check)),
                      ("f64_single_sweep", dict(t=1))):
-        j = Jacobi(box, **kw)
-        r0, _ = j.residual()
+        j = Jacobi(box, layout=layout, **kw)
+        if r0 is None:
+            r0, _ = j.residual()
+            res["r0"] = r0
         torch.cuda.synchronize()
         a = time.perf_counter()
-        total = 0
-        while True:
-            done, fin = j.solve(rel_tol, 64 * check, check, r0)
+        total, hist = 0, []
+        fin = r0
+        stop = target_sweeps if name != "f64_blocked" else None
+        if name == "f64_single_sweep":
+            stop = 8 * check
+        while fin > rel_tol * r0:
+            chunk = 16 * check
+            if stop is not None:
+                chunk = min(chunk, stop - total)
+                if chunk <= 0:
+                    break
+            done, fin = j.solve(rel_tol, chunk, check, r0)
             total += done
-            if fin <= rel_tol * r0 or total >= 50_000_000:
-                break
+            hist.append((total, fin))
+            el = time.perf_counter() - a
             print("time-to-tol n=%d %s: %d sweeps, ||r||/||r0|| = %.3e, %.1f s"
-                  % (n, name, total, fin / r0, time.perf_counter() - a),
-                  file=sys.stderr, flush=True)
+                  % (n, name, total, fin / r0, el), file=sys.stderr, flush=True)
+            if budget > 0 and el > budget and name == "f64_blocked":
+                break
         dt = time.perf_counter() - a
+        rate = n ** 3 * total / dt / 1e9
+        rec = {"sweeps": total, "seconds": round(dt, 3), "final_l2": fin,
+               "final_rel": fin / r0, "glups": round(rate, 1), "converged": fin <= rel_tol * r0}
+        if name == "f64_blocked":
+            target_sweeps = total
+            if not rec["converged"] and len(hist) >= 17:
+                (s0, f0), (s1, f1) = hist[-17], hist[-1]
+                rho = (f1 / f0) ** (1.0 / (s1 - s0))
+                more = math.log(rel_tol * r0 / f1) / math.log(rho)
+                more = int(math.ceil(more / check)) * check
+                rec["extrapolated"] = {
+                    "decay_per_sweep": rho, "sweeps": total + more,
+                    "seconds": round(dt + n ** 3 * more / (rate * 1e9), 1),
+                    "how": "remaining sweeps at the residual decay of the last 16 checks, "
+                           "at the measured GLUP/s"}
+            fields["f64"] = j.current().clone()
+        elif name == "f32_refined":
+            fields["f32"] = j.current().clone()
+            base = res["f64_blocked"]
+            if not base["converged"]:
+                ex = base["extrapolated"]
+                rec["extrapolated"] = {
+                    "sweeps": ex["sweeps"],
+                    "seconds": round(dt + n ** 3 * (ex["sweeps"] - total) / (rate * 1e9), 1),
+                    "how": "the FP64 run's extrapolated sweep count at this form's GLUP/s"}
+        else:
+            want = res["f64_blocked"].get("extrapolated", res["f64_blocked"])["sweeps"]
+            rec = {"sweeps_timed": total, "seconds_timed": round(dt, 3),
+                   "glups": round(rate, 1), "sweeps": want,
+                   "seconds_extrapolated": round(n ** 3 * want / (rate * 1e9), 1),
+                   "how": "timed on %d sweeps; the blocked form's sweep count at this rate "
+                          "(same iterates bit for bit)" % total}
         j.close()
-        res[name] = {"sweeps": total, "seconds": round(dt, 3), "final_l2": fin,
-                     "glups": round(n ** 3 * total / dt / 1e9, 1)}
+        res[name] = rec
+    # errors: FP32-refined vs FP64 at equal sweeps, both vs the closed form
+    ustar = _closed_form(torch, n, modes)
+    bound = lambda l2: l2 / (6.0 * (1.0 - mu1))  # noqa: E731
+    res["errors"] = {
+        "f32_refined_vs_f64": _field_errors(torch, fields["f32"], fields["f64"]),
+        "f64_vs_closed_form": _field_errors(torch, fields["f64"], ustar),
+        "f32_refined_vs_closed_form": _field_errors(torch, fields["f32"], ustar),
+        "residual_bound_l2_f64": bound(res["f64_blocked"]["final_l2"]),
+        "residual_bound_l2_f32_refined": bound(res["f32_refined"]["final_l2"]),
+        "closed_form_l2": float(torch.linalg.vector_norm(ustar[1:-1, 1:-1, 1:-1])),
+        "note": "at equal sweep counts; the bound ||r||/(6(1-mu1)) holds for ||u - u*||_2",
+    }
+    d64 = torch.linalg.vector_norm((fields["f64"] - ustar)[1:-1, 1:-1, 1:-1])
+    res["errors"]["f64_abs_l2_vs_closed_form"] = float(d64)
+    del fields, ustar, box
     torch.cuda.empty_cache()
     return res
 

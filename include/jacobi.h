@@ -70,7 +70,11 @@ typedef struct {
     int64_t nx, ny, nz;  /* interior dims, each >= 1; box is (n+2) per axis */
     int32_t dtype;       /* jacobi_dtype */
     int32_t layout;      /* jacobi_layout */
-    int32_t t;           /* sweeps per trip, 1..8 (0 = library default 4) */
+    int32_t t;           /* sweeps per trip, 1..8; 0 = autotune for A/B FP64
+                            handles with default tile and segments (the first
+                            jacobi_sweep of >= 96 sweeps times the candidate
+                            (t, tile) configurations on real sweeps, keeps the
+                            fastest; t = 5 until then), else 4 */
     int32_t tile_rows;   /* j-rows per tile: 0 = default for t, else one of
                             the compiled shapes (jacobi_tile_supported) */
     int32_t rows_per_wave; /* 0 = default; with tile_rows selects the shape */
@@ -148,6 +152,13 @@ int jacobi_current(jacobi_t *h, void **origin, int64_t strides[3]);
 /* Sweeps applied so far and the trip configuration in use. */
 int jacobi_info(jacobi_t *h, int64_t *sweeps_done, int32_t *t,
                 int32_t *tile_rows, int32_t *seg_len);
+
+/* The autotuner's measurements of a t = 0 handle: up to `cap` entries of
+ * (t, tile_rows, rows_per_wave, GLUP/s); *n = entries made (0 before the
+ * tuning has run); optional *tune_ms = the tuning's duration on the stream. */
+int jacobi_tune_log(jacobi_t *h, int32_t cap, int32_t *t, int32_t *tile_rows,
+                    int32_t *rows_per_wave, double *glups, int32_t *n,
+                    double *tune_ms);
 
 /* Releases the handle; never frees caller buffers. */
 int jacobi_destroy(jacobi_t *h);

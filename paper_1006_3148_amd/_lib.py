@@ -107,6 +107,10 @@ _SIGS = {
                               ctypes.c_int),
     "jacobi_batch_sync": ([_h], ctypes.c_int),
     "jacobi_batch_destroy": ([_h], ctypes.c_int),
+    "jacobi_tune_log": ([_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "jacobi_residual_noalloc": ([ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),

@@ -124,6 +124,15 @@ struct jacobi_s {
     int64_t sweeps = 0;
     int64_t spin_limit = 1 << 25;
     Plan plans[9];           // plans[T] for T = 1..t
+    // t = 0 (A/B FP64): candidates are timed on the first jacobi_sweep call
+    // with enough sweeps; until then trips use the default t.
+    bool tune_pending = false;
+    double tune_ms = 0;
+    struct TuneEntry {
+        TripConfig cfg;
+        double glups;
+    };
+    std::vector<TuneEntry> tune_log;
     // workspace carve-up
     char* ws = nullptr;
     int* ticket = nullptr;
@@ -161,6 +170,16 @@ struct Layout {
     int64_t flag_ints;
 };
 
+// Autotuner of single A/B FP64 handles created with t = 0: (T, rows per
+// wave, waves) candidates, each timed on one warm-up and two timed trips of
+// real sweeps; the default until the tuning has run is kTuneDefaultT.
+const TripConfig kTuneCandidates[] = {
+    {3, 4, 12}, {4, 3, 12}, {4, 4, 8}, {5, 4, 8}, {5, 3, 12}, {6, 3, 12},
+};
+constexpr int kTuneMaxT = 6;
+constexpr int64_t kTuneSweeps = 96;  // >= 3 trips of every candidate
+constexpr int kTuneDefaultT = 5;
+
 constexpr int kMaxTeams = 1024;
 
 int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
@@ -176,7 +195,9 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
         return fail(JACOBI_EINVAL, "unknown dtype %d", d->dtype);
     if (d->layout != JACOBI_LAYOUT_AB && d->layout != JACOBI_LAYOUT_COMPRESSED)
         return fail(JACOBI_EINVAL, "unknown layout %d", d->layout);
-    const int t = d->t == 0 ? 4 : d->t;
+    const bool tune = d->t == 0 && d->layout == JACOBI_LAYOUT_AB && d->dtype == JACOBI_F64 &&
+                      d->tile_rows == 0 && d->rows_per_wave == 0 && d->seg_len == 0;
+    const int t = d->t == 0 ? (tune ? kTuneMaxT : 4) : d->t;
     if (t < 1 || t > 8)
         return fail(JACOBI_EUNSUPPORTED,
                     "sweeps per trip t=%d not supported (1..8)", t);
@@ -213,6 +234,14 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                         cfg.R * cfg.W,
                         comp ? " (compressed needs tiles and segments >= 2t)" : "");
         max_tiles = std::max<int64_t>(max_tiles, plans[T].ntiles);
+    }
+    if (tune) {
+        for (const TripConfig& c : kTuneCandidates) {
+            Plan pl;
+            if (trip_config_supported(0, c) &&
+                make_plan(d->nx, d->ny, d->nz, c, 0, false, kCUs, &pl))
+                max_tiles = std::max<int64_t>(max_tiles, pl.ntiles);
+        }
     }
     *t_out = t;
     Layout L{};
@@ -421,6 +450,61 @@ int replay_f64(jacobi_t* h, int64_t n)
     return JACOBI_OK;
 }
 
+// Times every candidate on real sweeps of the iterate (A/B FP64 sweeps are
+// bitwise the same for every configuration) and keeps the fastest.
+int autotune_single(jacobi_t* h, int64_t* n)
+{
+    hipEvent_t a = nullptr, b = nullptr, t0 = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventRecord(t0, h->stream);
+    const double cells = (double)h->d.nx * h->d.ny * h->d.nz;
+    double best = -1;
+    Plan best_plan = h->plans[h->t];
+    for (const TripConfig& c : kTuneCandidates) {
+        if (e != hipSuccess) break;
+        Plan pl;
+        if (!trip_config_supported(0, c) ||
+            !make_plan(h->d.nx, h->d.ny, h->d.nz, c, 0, false, kCUs, &pl))
+            continue;
+        const Plan saved = h->plans[c.T];
+        h->plans[c.T] = pl;
+        float ms = 0;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+            if (r == 1) e = hipEventRecord(a, h->stream);
+            if (e == hipSuccess)
+                e = launch_trip(h, c.T, false, grid_origin(h, h->cur),
+                                grid_origin(h, 1 - h->cur), nullptr, h->px, h->py, 0, 1);
+            h->cur ^= 1;
+        }
+        if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        h->plans[c.T] = saved;
+        h->sweeps += 3 * c.T;
+        *n -= 3 * c.T;
+        if (e != hipSuccess) break;
+        const double glups = cells * 2 * c.T / (ms * 1e-3) / 1e9;
+        h->tune_log.push_back({c, glups});
+        if (glups > best) {
+            best = glups;
+            best_plan = pl;
+        }
+    }
+    float total = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&total, t0, b);
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    if (t0) hipEventDestroy(t0);
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    h->tune_ms = total;
+    h->t = best_plan.cfg.T;
+    h->plans[h->t] = best_plan;
+    h->tune_pending = false;
+    return JACOBI_OK;
+}
+
 int check_pending(jacobi_t* h)
 {
     int errw = 0;
@@ -509,6 +593,10 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     if (!h) return fail(JACOBI_EINVAL, "out of host memory");
     h->d = *d;
     h->t = t;
+    if (d->t == 0 && t == kTuneMaxT) {
+        h->tune_pending = true;
+        h->t = kTuneDefaultT;
+    }
     for (int T = 1; T <= t; ++T) h->plans[T] = plans[T];
     const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
     h->room = comp ? 2 * t : 0;
@@ -573,6 +661,10 @@ int jacobi_sweep(jacobi_t* h, int64_t n_steps)
 {
     if (!h) return fail(JACOBI_EINVAL, "null handle");
     if (n_steps < 0) return fail(JACOBI_EINVAL, "n_steps < 0");
+    if (h->tune_pending && n_steps >= kTuneSweeps) {
+        int rc = autotune_single(h, &n_steps);
+        if (rc != JACOBI_OK) return rc;
+    }
     if (h->d.dtype == JACOBI_F64 && h->d.use_graph && h->d.layout == JACOBI_LAYOUT_AB &&
         n_steps > 0)
         return replay_f64(h, n_steps);
@@ -651,6 +743,23 @@ int jacobi_info(jacobi_t* h, int64_t* sweeps_done, int32_t* t,
     if (t) *t = h->t;
     if (tile_rows) *tile_rows = h->plans[h->t].cfg.R * h->plans[h->t].cfg.W;
     if (seg_len) *seg_len = h->plans[h->t].seg_len;
+    return JACOBI_OK;
+}
+
+int jacobi_tune_log(jacobi_t* h, int32_t cap, int32_t* t, int32_t* tile_rows,
+                    int32_t* rows_per_wave, double* glups, int32_t* n, double* tune_ms)
+{
+    if (!h || !n || cap < 0) return fail(JACOBI_EINVAL, "null argument");
+    const int m = (int)std::min<size_t>((size_t)cap, h->tune_log.size());
+    for (int q = 0; q < m; ++q) {
+        const auto& e = h->tune_log[q];
+        if (t) t[q] = e.cfg.T;
+        if (tile_rows) tile_rows[q] = e.cfg.R * e.cfg.W;
+        if (rows_per_wave) rows_per_wave[q] = e.cfg.R;
+        if (glups) glups[q] = e.glups;
+    }
+    *n = (int32_t)h->tune_log.size();
+    if (tune_ms) *tune_ms = h->tune_ms;
     return JACOBI_OK;
 }
 

@@ -72,7 +72,7 @@ __device__ __forceinline__ void static_for(F&& f)
 // Spin until every dependee's progress word is >= need (or the bounded spin
 // runs out, which raises the error word).  Out of line, so that the rare wait
 // does not split the straight-line step code of the caller.
-__device__ __attribute__((noinline)) int wait_progress(int* flags, int dep, int need,
+__device__ __forceinline__ int wait_progress(int* flags, int dep, int need,
                                                       long long spin_limit, int* err)
 {
     const int lane = threadIdx.x & 63;
@@ -496,7 +496,11 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             __syncthreads();  // previous tile finished with tile_sh and xch
             if (threadIdx.x == 0) tile_sh = atomicAdd(p.ticket, 1);
             __syncthreads();
-            const int t = tile_sh;
+            // Uniform across the workgroup: read it into a scalar register,
+            // so that the per-plane buffer descriptors built from it stay
+            // scalar (otherwise every buffer access becomes a waterfall loop
+            // over the lanes).
+            const int t = __builtin_amdgcn_readfirstlane(tile_sh);
             if (MODE == 3) {
                 if (t >= p.ntiles * p.teams) return;
                 team = t / p.ntiles;
@@ -517,7 +521,7 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
                     hi = mid - 1;
             }
             const BatchProblem& bp = p.table[lo];
-            const int par = *p.parity & 1;
+            const int par = __builtin_amdgcn_readfirstlane(*p.parity) & 1;
             g.src = bp.grid[par];
             g.dst = bp.grid[par ^ 1];
             g.rhs = bp.rhs;
@@ -570,7 +574,7 @@ template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE>
 hipError_t launch_mode(const TripParams& p, hipStream_t s)
 {
     const dim3 block(64 * W);
-    if (MODE == 0) {
+    if constexpr (MODE == 0) {
         hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 0>),
                            dim3(p.ntiles), block, 0, s, p);
         return hipGetLastError();

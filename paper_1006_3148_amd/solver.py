@@ -126,6 +126,20 @@ class Jacobi:
         return {"sweeps": s.value, "t": t.value, "tile_rows": rows.value,
                 "seg_len": seg.value}
 
+    def tune_log(self):
+        """Autotuner measurements of a t=0 handle and the tuning time (ms)."""
+        cap = 32
+        t = (ctypes.c_int32 * cap)()
+        rows = (ctypes.c_int32 * cap)()
+        rpw = (ctypes.c_int32 * cap)()
+        g = (ctypes.c_double * cap)()
+        n = ctypes.c_int32()
+        ms = ctypes.c_double()
+        check(lib.jacobi_tune_log(self._h, cap, t, rows, rpw, g, ctypes.byref(n),
+                                  ctypes.byref(ms)))
+        return ([{"t": t[q], "tile_rows": rows[q], "rows_per_wave": rpw[q],
+                  "glups": g[q]} for q in range(min(n.value, cap))], ms.value)
+
     def current(self) -> torch.Tensor:
         """Strided torch view of the current iterate (nz+2, ny+2, nx+2)."""
         origin = ctypes.c_void_p()

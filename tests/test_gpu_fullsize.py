@@ -16,7 +16,7 @@ def _same(a, b):
 
 # ("ab", 5) is the headline bench configuration (4 x 8 tile, one 514-plane
 # segment per tile column).
-@pytest.mark.parametrize("layout,t", [("ab", 5), ("ab", 3), ("compressed", 5)])
+@pytest.mark.parametrize("layout,t", [("ab", 5), ("ab", 3), ("compressed", 5), ("ab", 0)])
 def test_512cube_200_sweeps_bitwise(layout, t):
     from paper_1006_3148_amd import Jacobi
     print("case 512^3 x 200 %s t=%d" % (layout, t), flush=True)

@@ -239,3 +239,24 @@ def test_solve_with_graph_replay_matches_eager():
     assert done == wdone
     _assert_same(got, want, "solve with graphs")
     assert abs(fin - wrn) <= 1e-12 * wrn
+
+
+def test_autotune_t0_picks_fastest_and_stays_bitwise():
+    """t=0 (A/B FP64): the first call of >= 96 sweeps times every candidate on
+    real sweeps, keeps the fastest, and the result is bitwise the plain
+    sweeps."""
+    from paper_1006_3148_amd import Jacobi
+    box = synth.uniform_box(150, 97, 41, seed=320)
+    print("case autotune t=0 150x97x41", flush=True)
+    j = Jacobi(box, t=0)
+    j.sweep(10)                    # below the tuning threshold: default t
+    assert j.tune_log()[0] == []
+    j.sweep(200)
+    log, ms = j.tune_log()
+    info = j.info()
+    got = j.box()
+    j.close()
+    assert len(log) == 6 and ms > 0
+    best = max(log, key=lambda e: e["glups"])
+    assert (info["t"], info["tile_rows"]) == (best["t"], best["tile_rows"])
+    _assert_same(got, oracle.sweeps_f64(box, 210), "autotune t=0")
