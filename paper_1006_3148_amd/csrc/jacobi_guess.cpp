@@ -52,7 +52,7 @@ bool plan(int64_t n, int L, Layout* lay)
     l.loss = add(off, 8);
     l.lpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 8);
     l.gpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 17 * 4);
-    l.wpart = add(off, (size_t)512 * (kConvW + kC) * 4);
+    l.wpart = add(off, (size_t)kMaxWgradBlocks * (kConvW + kC) * 4);
     l.sines = add(off, (size_t)2 * n * 4);
     l.mpart = add(off, (size_t)head_blocks((int64_t)vox(0)) * 8 * 8);
     l.acoef = add(off, 8 * 8);
@@ -279,13 +279,13 @@ int jg_backward(jg_net* h, const float* target, double* loss)
         e = conv_bwd_weight(A(h, l.da[lev]), d, F(h, l.ga[lev]), d, 1, wpart,
                             G(h, ix.dec_b[lev]), h->s);
         if (e == hipSuccess)
-            e = conv_bwd_data(F(h, l.ga[lev]), d, WT(h, ix.dec_b[lev]), F(h, l.gb[lev]), d, 1,
+            e = conv_bwd_data(F(h, l.ga[lev]), d, W(h, ix.dec_b[lev]), WT(h, ix.dec_b[lev]), F(h, l.gb[lev]), d, 1,
                               false, A(h, l.da[lev]), h->s);
         if (e == hipSuccess)
             e = conv_bwd_weight(A(h, l.sm[lev]), d, F(h, l.gb[lev]), d, 1, wpart,
                                 G(h, ix.dec_a[lev]), h->s);
         if (e == hipSuccess)
-            e = conv_bwd_data(F(h, l.gb[lev]), d, WT(h, ix.dec_a[lev]), F(h, l.gs[lev]), d, 1,
+            e = conv_bwd_data(F(h, l.gb[lev]), d, W(h, ix.dec_a[lev]), WT(h, ix.dec_a[lev]), F(h, l.gs[lev]), d, 1,
                               false, nullptr, h->s);
         // the upsampled input came from dec_b of level lev+1, or from the
         // bottom encoder output
@@ -302,20 +302,20 @@ int jg_backward(jg_net* h, const float* target, double* loss)
             e = conv_bwd_weight(A(h, l.eb[lev]), d, F(h, l.ga[lev + 1]), dd, 2, wpart,
                                 G(h, ix.down[lev]), h->s);
             if (e == hipSuccess)
-                e = conv_bwd_data(F(h, l.ga[lev + 1]), dd, WT(h, ix.down[lev]), F(h, l.gs[lev]),
+                e = conv_bwd_data(F(h, l.ga[lev + 1]), dd, W(h, ix.down[lev]), WT(h, ix.down[lev]), F(h, l.gs[lev]),
                                   d, 2, true, A(h, l.eb[lev]), h->s);
             cur = F(h, l.gs[lev]);
         }
         if (e == hipSuccess)
             e = conv_bwd_weight(A(h, l.ea[lev]), d, cur, d, 1, wpart, G(h, ix.enc_b[lev]), h->s);
         if (e == hipSuccess)
-            e = conv_bwd_data(cur, d, WT(h, ix.enc_b[lev]), F(h, l.gb[lev]), d, 1, false,
+            e = conv_bwd_data(cur, d, W(h, ix.enc_b[lev]), WT(h, ix.enc_b[lev]), F(h, l.gb[lev]), d, 1, false,
                               A(h, l.ea[lev]), h->s);
         const uint16_t* in = lev == 0 ? A(h, l.in) : A(h, l.dn[lev - 1]);
         if (e == hipSuccess)
             e = conv_bwd_weight(in, d, F(h, l.gb[lev]), d, 1, wpart, G(h, ix.enc_a[lev]), h->s);
         if (e == hipSuccess && lev > 0)
-            e = conv_bwd_data(F(h, l.gb[lev]), d, WT(h, ix.enc_a[lev]), F(h, l.ga[lev]), d, 1,
+            e = conv_bwd_data(F(h, l.gb[lev]), d, W(h, ix.enc_a[lev]), WT(h, ix.enc_a[lev]), F(h, l.ga[lev]), d, 1,
                               false, A(h, l.dn[lev - 1]), h->s);
     }
     if (e != hipSuccess) return hip_fail(e, "network backward");
@@ -384,7 +384,8 @@ size_t layer_ws(int64_t d, int stride, size_t* part_off)
 {
     const int dout = (int)(d / stride);
     *part_off = (size_t)round_up(kConvW * 2, 256);
-    return *part_off + (size_t)round_up((int64_t)wgrad_blocks(dout) * kConvP * 4, 256);
+    (void)dout;
+    return *part_off + (size_t)round_up((int64_t)kMaxWgradBlocks * kConvP * 4, 256);
 }
 
 int layer_args(const void* a, const void* b, const void* c, int64_t d, int stride)
@@ -441,7 +442,7 @@ int jg_conv3_backward_data(const float* dy, int64_t d, const uint16_t* w, int32_
     uint16_t* wt = static_cast<uint16_t*>(workspace);
     hipError_t e = transpose_w(w, wt, s);
     if (e == hipSuccess)
-        e = conv_bwd_data(dy, (int)(d / stride), wt, dx, (int)d, stride, false, nullptr, s);
+        e = conv_bwd_data(dy, (int)(d / stride), w, wt, dx, (int)d, stride, false, nullptr, s);
     return e == hipSuccess ? JACOBI_OK : hip_fail(e, "conv data gradient");
 }
 

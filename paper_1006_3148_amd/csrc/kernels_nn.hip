@@ -281,15 +281,26 @@ __global__ __launch_bounds__(256) void conv_bwd_weight_kernel(
             ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
 }
 
-// Sum of per-block partials (fixed order) added into the FP32 gradient.
+// Sum of per-block partials added into the FP32 gradient, in a fixed order:
+// a workgroup owns 16 consecutive entries; its 16 groups of 16 threads each
+// sum every 16th block for one entry (group g takes blocks g, g+16, ...),
+// then a fixed tree over the 16 groups.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(
     const float* __restrict__ part, int blocks, int width, float* __restrict__ grad)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= width) return;
+    __shared__ float sh[16][17];
+    const int e = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int q = blockIdx.x * 16 + e;
     float s = 0.f;
-    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * width + q];
-    grad[q] += s;
+    if (q < width)
+        for (int b = g; b < blocks; b += 16) s += part[(int64_t)b * width + q];
+    sh[g][e] = s;
+    __syncthreads();
+    for (int w = 8; w > 0; w >>= 1) {
+        if (g < w) sh[g][e] += sh[g + w][e];
+        __syncthreads();
+    }
+    if (g == 0 && q < width) grad[q] += sh[0][e];
 }
 
 // ----------------------------------------------------- up / skip add ----
@@ -587,6 +598,7 @@ hipError_t lift(const double* box, int n, uint16_t* x, float* blend, hipStream_t
 hipError_t conv_fwd(const uint16_t* x, int din, const uint16_t* w, const float* b,
                     uint16_t* y, int stride, bool relu, hipStream_t s)
 {
+    if (stride == 1 && relu) return conv_fwd_s1(x, din, w, b, y, s);
     const int dout = din / stride;
     const int64_t tiles = (int64_t)dout * dout * ((dout + 15) / 16);
     const dim3 grid(blocks_for(tiles, 4));
@@ -607,6 +619,7 @@ hipError_t conv_fwd(const uint16_t* x, int din, const uint16_t* w, const float* 
 hipError_t conv_fwd_f32(const uint16_t* x, int din, const uint16_t* w, const float* b,
                         float* y, int stride, hipStream_t s)
 {
+    if (stride == 1) return conv_fwd_s1_f32(x, din, w, b, y, s);
     const int dout = din / stride;
     const int64_t tiles = (int64_t)dout * dout * ((dout + 15) / 16);
     const dim3 grid(blocks_for(tiles, 4));
@@ -623,10 +636,11 @@ hipError_t transpose_w(const uint16_t* w, uint16_t* wt, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* wt, float* dx,
-                         int din, int stride, bool accum, const uint16_t* mask,
+hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* w, const uint16_t* wt,
+                         float* dx, int din, int stride, bool accum, const uint16_t* mask,
                          hipStream_t s)
 {
+    if (stride == 1) return conv_bwd_data_s1(dy, din, w, dx, accum, mask, s);
     const int64_t tiles = (int64_t)din * din * ((din + 15) / 16);
     const dim3 grid(blocks_for(tiles, 4));
     if (stride == 1)
@@ -646,9 +660,19 @@ int wgrad_blocks(int dout)
     return (int)(b < 1 ? 1 : b);
 }
 
+hipError_t reduce_partials(const float* part, int blocks, float* grad, hipStream_t s)
+{
+    const int width = 27 * 256 + 16;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(width, 16)), dim3(256), 0, s,
+                       part, blocks, width, grad);
+    return hipGetLastError();
+}
+
 hipError_t conv_bwd_weight(const uint16_t* x, int din, const float* dy, int dout,
                            int stride, float* part, float* grad_w_b, hipStream_t s)
 {
+    if (stride == 1 && wgrad_s1_blocks(din, nullptr) > 0)
+        return conv_bwd_weight_s1(x, dy, din, part, grad_w_b, s);
     const int blocks = wgrad_blocks(dout);
     const int64_t nchunk = ((int64_t)dout * dout * dout + 15) / 16;
     const int cpw = (int)((nchunk + (int64_t)blocks * 4 - 1) / ((int64_t)blocks * 4));
@@ -658,10 +682,9 @@ hipError_t conv_bwd_weight(const uint16_t* x, int din, const float* dy, int dout
     else
         hipLaunchKernelGGL((conv_bwd_weight_kernel<2>), dim3(blocks), dim3(256), 0, s, x, din,
                            dy, dout, part, cpw);
-    const int width = 27 * 256 + 16;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks_for(width, 256)), dim3(256), 0, s,
-                       part, blocks, width, grad_w_b);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_partials(part, blocks, grad_w_b, s);
 }
 
 hipError_t up_add(const uint16_t* x, const uint16_t* skip, uint16_t* out, int d,

@@ -19,9 +19,24 @@ hipError_t conv_fwd_f32(const uint16_t* x, int din, const uint16_t* w, const flo
                         float* y, int stride, hipStream_t s);
 // wt[t][ci][co] = w[t][co][ci] for one layer (bf16).
 hipError_t transpose_w(const uint16_t* w, uint16_t* wt, hipStream_t s);
-hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* wt, float* dx,
-                         int din, int stride, bool accum, const uint16_t* mask,
+// w: [27][Cout][Cin] (stride 1), wt: its per-tap transpose (stride 2).
+hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* w, const uint16_t* wt,
+                         float* dx, int din, int stride, bool accum, const uint16_t* mask,
                          hipStream_t s);
+// Stride-1 convolutions streamed through LDS (kernels_conv.hip).
+hipError_t conv_fwd_s1(const uint16_t* x, int d, const uint16_t* w, const float* b,
+                       uint16_t* y, hipStream_t s);
+hipError_t conv_fwd_s1_f32(const uint16_t* x, int d, const uint16_t* w, const float* b,
+                           float* y, hipStream_t s);
+hipError_t conv_bwd_data_s1(const float* dy, int d, const uint16_t* w, float* dx, bool accum,
+                            const uint16_t* mask, hipStream_t s);
+// Weight-gradient partials: at most kMaxWgradBlocks blocks of kConvP floats.
+constexpr int kMaxWgradBlocks = 512;
+int wgrad_s1_blocks(int d, int* zseg);
+hipError_t conv_bwd_weight_s1(const uint16_t* x, const float* dy, int d, float* part,
+                              float* grad_w_b, hipStream_t s);
+// grad[q] += sum over blocks b (fixed order) of part[b * kConvP + q].
+hipError_t reduce_partials(const float* part, int blocks, float* grad, hipStream_t s);
 int wgrad_blocks(int dout);
 hipError_t conv_bwd_weight(const uint16_t* x, int din, const float* dy, int dout,
                            int stride, float* part, float* grad_w_b, hipStream_t s);

@@ -211,6 +211,37 @@ def evaluate(net: GuessNet, n: int, seeds, rel_tol: float = 1e-8,
     return res
 
 
+def time_layers(n: int, reps: int = 10):
+    """One stride-1 convolution at n^3 through the single-layer entry points
+    (forward, data gradient, weight gradient): ms per call (HIP events) and
+    TFLOP/s at 2 x 27 x 16 x 16 flops per voxel, against the 2.5 PFLOP/s
+    dense BF16 MFMA peak."""
+    from . import guess
+    g = torch.Generator(device="cuda").manual_seed(0)
+    xb = torch.randn((n, n, n, 16), device="cuda", generator=g).relu().to(torch.bfloat16)
+    wb = (0.1 * torch.randn((27, 16, 16), device="cuda", generator=g)).to(torch.bfloat16)
+    x, w = xb.view(torch.int16), wb.view(torch.int16)
+    b = torch.zeros(16, device="cuda")
+    dy = torch.randn((n, n, n, 16), device="cuda", generator=g)
+    flop = 2.0 * 27 * 16 * 16 * n ** 3
+    out = {}
+    for name, fn in (("forward", lambda: guess.conv3_forward(x, w, b)),
+                     ("data_grad", lambda: guess.conv3_backward_data(dy, w)),
+                     ("weight_grad", lambda: guess.conv3_backward_weight(x, dy))):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        out[name] = {"ms": round(ms, 4), "tflops": round(flop / (ms * 1e-3) / 1e12, 1),
+                     "frac_bf16_peak": round(flop / (ms * 1e-3) / 2.5e15, 4)}
+    return out
+
+
 def main(argv=None):
     import argparse
     import json
@@ -252,7 +283,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     step = (time.perf_counter() - t0) / 5
     report = {"n": a.n, "levels": a.levels, "forward_ms": fwd * 1e3,
-              "train_step_ms": step * 1e3}
+              "train_step_ms": step * 1e3, "layers": time_layers(a.n)}
     log(json.dumps(report))
     if a.time_only:
         return report
