@@ -42,6 +42,9 @@ def parse():
                     help="only measure time to 1e-8 at N^3 and print it as JSON")
     ap.add_argument("--tts-budget", type=float, default=0.0, metavar="S",
                     help="with --tts-only: seconds per form before extrapolating")
+    ap.add_argument("--mg-tts", type=int, default=0, metavar="N",
+                    help="only measure the multigrid-corrected time to 1e-8 at N^3 "
+                         "(N = 2^k - 1)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--quick", action="store_true",
@@ -198,6 +201,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"probe": "copy", "bytes_read": a.numel() * 8,
                           "bytes_written": b.numel() * 8, "launches": 5}))
+        return
+    if args.mg_tts:
+        print(json.dumps({"multigrid_time_to_1e-8": bench_multigrid_tts(torch, args.mg_tts)}),
+              flush=True)
         return
     if args.tts_only:
         res = bench_time_to_tol(torch, args.tts_only, args.t or DEFAULT_T,
@@ -535,6 +542,40 @@ def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024, budget=0.0, layout=
     del fields, ustar, box
     torch.cuda.empty_cache()
     return res
+
+
+def bench_multigrid_tts(torch, n, rel_tol=1e-8):
+    """Time to ||r|| <= 1e-8 ||r0|| with the multigrid-corrected refinement
+    (one FP32 V(2,2)-cycle of weighted-Jacobi smoothing per FP64 outer step)
+    on an n^3 interior, n = 2^k - 1, sine-mode faces (seed 3), zero start;
+    checking after every outer step.  Reports the steps, the seconds, the
+    error against the closed-form solution and the residual bound."""
+    import math
+    import synth
+    from paper_1006_3148_amd import Jacobi
+    box = torch.from_numpy(synth.sine_face_box(n, n, n, seed=3)).cuda()
+    mu1 = math.cos(math.pi / (n + 1))
+    j = Jacobi(box, dtype="f32_multigrid")
+    r0, _ = j.residual()
+    j.sweep(1)             # warm-up step (first launches of every kernel)
+    j.close()
+    j = Jacobi(box, dtype="f32_multigrid")
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    steps, fin = j.solve(rel_tol, 200, 1, r0)
+    dt = time.perf_counter() - a
+    u = j.current().clone()
+    j.close()
+    ustar = _closed_form(torch, n, synth.sine_face_modes(3))
+    err = _field_errors(torch, u, ustar)
+    err["abs_l2"] = float(torch.linalg.vector_norm((u - ustar)[1:-1, 1:-1, 1:-1]))
+    err["residual_bound_l2"] = fin / (6.0 * (1.0 - mu1))
+    del u, ustar, box
+    torch.cuda.empty_cache()
+    return {"n": n, "rel_tol": rel_tol, "outer_steps": steps, "seconds": round(dt, 4),
+            "final_rel": fin / r0, "r0": r0, "vs_closed_form": err,
+            "method": "FP64 residual + FP32 V(2,2)-cycle, weighted Jacobi w=6/7 "
+                      "(trip kernel, t=2 trips), full weighting, trilinear prolongation"}
 
 
 def _kernel_hash():

@@ -56,9 +56,18 @@ typedef enum {
 } jacobi_status;
 
 typedef enum {
-    JACOBI_F64 = 0,        /* FP64 sweeps */
-    JACOBI_F32_REFINED = 1 /* FP32 sweeps of the correction equation, FP64
-                              residual and FP64 defect-correction update */
+    JACOBI_F64 = 0,         /* FP64 sweeps */
+    JACOBI_F32_REFINED = 1, /* FP32 sweeps of the correction equation, FP64
+                               residual and FP64 defect-correction update */
+    JACOBI_F32_MULTIGRID = 2 /* as JACOBI_F32_REFINED, but the correction
+                               equation is solved by one FP32 multigrid
+                               V(2,2)-cycle whose smoother is the weighted
+                               Jacobi sweep e' = e + (6/7)(v - e), v the
+                               Eq. (1) update plus the right-hand side (the
+                               Jacobi update as multigrid smoother,
+                               Sect. 1.1); AB layout, n^3 interior with
+                               n = 2^k - 1; jacobi_sweep(h, n) makes n outer
+                               steps and t is ignored */
 } jacobi_dtype;
 
 typedef enum {

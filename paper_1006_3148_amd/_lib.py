@@ -28,7 +28,7 @@ STATUS = {
     -5: "JACOBI_ETIMEOUT",
     -6: "JACOBI_ESTATE",
 }
-F64, F32_REFINED = 0, 1
+F64, F32_REFINED, F32_MULTIGRID = 0, 1, 2
 LAYOUT_AB, LAYOUT_COMPRESSED = 0, 1
 
 

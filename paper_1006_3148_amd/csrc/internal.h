@@ -50,6 +50,9 @@ struct TripParams {
     int looseness;              // mode 3: d_u (< 0: no bound)
     int* done;                  // mode 3: per-team count of finished tiles,
                                 // stride kFlagStride ints (zeroed)
+    int weighted;               // FP32 with rhs: weighted sweeps (multigrid
+                                // smoother) with weight omega
+    float omega;
 };
 
 constexpr int kFlagStride = 32;  // ints per flag (128 B line each)
@@ -123,6 +126,13 @@ hipError_t launch_set_int(int* word, int value, hipStream_t s);
 hipError_t launch_copy_box_f64(const double* src, int64_t spx, int64_t spy,
                                double* dst, int64_t dpx, int64_t dpy, int nx2,
                                int ny2, int nz2, hipStream_t s);
+
+// Multigrid correction solve (kernels_mg.hip), FP32 dense (n+2)^3 boxes with
+// n = 2^k - 1: r = (fold(e nbrs) + rhs) - 6e; coarse rhs = 4 x full
+// weighting of r; e += trilinear prolongation of the coarse correction.
+hipError_t launch_mg_residual(const float* e, const float* rhs, float* r, int n, hipStream_t s);
+hipError_t launch_mg_restrict(const float* r, int n, float* rc, hipStream_t s);
+hipError_t launch_mg_prolong_add(const float* ec, float* e, int n, hipStream_t s);
 
 // Bandwidth probes: STREAM-like copy b[i] = a[i] and in-place update
 // a[i] += 1.0 (the paper's array-update benchmark).

@@ -145,6 +145,14 @@ struct jacobi_s {
     int* done = nullptr;     // per-team finished-tile counts (teams >= 2)
     float* e[2] = {nullptr, nullptr};
     float* rhs = nullptr;
+    // multigrid levels (level 0 = e, rhs above)
+    struct MgLevel {
+        int n;
+        float* e[2];
+        float* rhs;
+        Plan plan;  // FP32 trips of kMgT sweeps on this level
+    };
+    std::vector<MgLevel> mg;
     AuxProblem aux{};         // residual / refinement view of this problem
     // A/B FP64 graph replay (use_graph): trips are captured on `cap` once per
     // (sweep count, starting grid) and replayed on `stream`.
@@ -168,7 +176,19 @@ namespace {
 struct Layout {
     size_t partials_off, flags_off, done_off, e0_off, e1_off, rhs_off, total;
     int64_t flag_ints;
+    std::vector<size_t> mg_off;  // multigrid levels 1.. : e0, e1, rhs
 };
+
+// Multigrid correction solve (JACOBI_F32_MULTIGRID): V(kMgNu, kMgNu) cycles
+// of weighted FP32 sweeps (weight 6/7) down to an interior of at most
+// kMgCoarsest cells per axis, where kMgCoarse sweeps are made.
+constexpr int kMgT = 2;
+constexpr int kMgNu = 2;
+constexpr int kMgCoarse = 32;
+constexpr int kMgCoarsest = 3;
+constexpr float kMgOmega = 6.0f / 7.0f;
+
+bool mg_levels_ok(int64_t n) { return n >= 1 && ((n + 1) & n) == 0; }
 
 // Autotuner of single A/B FP64 handles created with t = 0: (T, rows per
 // wave, waves) candidates, each timed on one warm-up and two timed trips of
@@ -191,13 +211,21 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                     (long long)d->nx, (long long)d->ny, (long long)d->nz);
     if (d->nx > 65536 || d->ny > 65536 || d->nz > 65536)
         return fail(JACOBI_EINVAL, "interior dims must be <= 65536");
-    if (d->dtype != JACOBI_F64 && d->dtype != JACOBI_F32_REFINED)
+    if (d->dtype != JACOBI_F64 && d->dtype != JACOBI_F32_REFINED &&
+        d->dtype != JACOBI_F32_MULTIGRID)
         return fail(JACOBI_EINVAL, "unknown dtype %d", d->dtype);
+    const bool mg = d->dtype == JACOBI_F32_MULTIGRID;
+    if (mg && (d->layout != JACOBI_LAYOUT_AB || d->nx != d->ny || d->nx != d->nz ||
+               !mg_levels_ok(d->nx) || d->teams > 1))
+        return fail(JACOBI_EUNSUPPORTED,
+                    "the multigrid correction needs the AB layout and an n^3 interior with "
+                    "n = 2^k - 1 (got %lld x %lld x %lld)",
+                    (long long)d->nx, (long long)d->ny, (long long)d->nz);
     if (d->layout != JACOBI_LAYOUT_AB && d->layout != JACOBI_LAYOUT_COMPRESSED)
         return fail(JACOBI_EINVAL, "unknown layout %d", d->layout);
     const bool tune = d->t == 0 && d->layout == JACOBI_LAYOUT_AB && d->dtype == JACOBI_F64 &&
                       d->tile_rows == 0 && d->rows_per_wave == 0 && d->seg_len == 0;
-    const int t = d->t == 0 ? (tune ? kTuneMaxT : 4) : d->t;
+    const int t = mg ? kMgT : d->t == 0 ? (tune ? kTuneMaxT : 4) : d->t;
     if (t < 1 || t > 8)
         return fail(JACOBI_EUNSUPPORTED,
                     "sweeps per trip t=%d not supported (1..8)", t);
@@ -216,14 +244,14 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     int64_t max_tiles = 0;
     for (int T = 1; T <= t; ++T) {
         TripConfig cfg = default_cfg(T, comp);
-        if (T == t && (d->tile_rows > 0 || d->rows_per_wave > 0)) {
+        if (T == t && !mg && (d->tile_rows > 0 || d->rows_per_wave > 0)) {
             const int R = d->rows_per_wave > 0 ? d->rows_per_wave : 4;
             const int rows = d->tile_rows > 0 ? d->tile_rows : cfg.R * cfg.W;
             if (rows % R != 0)
                 return fail(JACOBI_EINVAL, "tile_rows must be a multiple of rows_per_wave");
             cfg = TripConfig{T, R, rows / R};
         }
-        if (!trip_config_supported(d->dtype == JACOBI_F32_REFINED, cfg))
+        if (!trip_config_supported(d->dtype != JACOBI_F64, cfg))
             return fail(JACOBI_EUNSUPPORTED,
                         "tile shape t=%d rows=%d rows_per_wave=%d is not compiled",
                         T, cfg.R * cfg.W, cfg.R);
@@ -257,13 +285,23 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     L.done_off = (size_t)round_up(L.flags_off + L.flag_ints * sizeof(int), 256);
     size_t end = L.done_off + (teams ? (size_t)d->teams * kFlagStride * sizeof(int) : 0);
     L.e0_off = L.e1_off = L.rhs_off = 0;
-    if (d->dtype == JACOBI_F32_REFINED) {
+    L.mg_off.clear();
+    if (d->dtype != JACOBI_F64) {
         const int64_t box = (d->nx + 2) * (d->ny + 2) * (d->nz + 2);
         const size_t fb = (size_t)round_up(box * (int64_t)sizeof(float), 256);
         L.e0_off = end;
         L.e1_off = end + fb;
         L.rhs_off = end + 2 * fb;
         end += 3 * fb;
+    }
+    if (mg) {
+        // coarser levels: e0, e1, rhs boxes each
+        for (int64_t n = (d->nx - 1) / 2; n >= 1; n = (n - 1) / 2) {
+            const size_t fb = (size_t)round_up((n + 2) * (n + 2) * (n + 2) * 4, 256);
+            L.mg_off.push_back(end);
+            end += 3 * fb;
+            if (n <= kMgCoarsest) break;
+        }
     }
     L.total = end;
     *lay = L;
@@ -450,6 +488,79 @@ int replay_f64(jacobi_t* h, int64_t n)
     return JACOBI_OK;
 }
 
+// `sweeps` weighted FP32 sweeps on multigrid level l (trips of kMgT); the
+// current buffer index is updated.
+hipError_t mg_smooth(jacobi_t* h, int l, int* cur, int sweeps)
+{
+    const jacobi_s::MgLevel& L = h->mg[l];
+    hipError_t e = hipSuccess;
+    for (int done = 0; done < sweeps && e == hipSuccess; done += kMgT) {
+        TripParams p{};
+        p.src = L.e[*cur];
+        p.dst = L.e[1 - *cur];
+        p.rhs = L.rhs;
+        p.px = p.rpx = L.n + 2;
+        p.py = p.rpy = (int64_t)(L.n + 2) * (L.n + 2);
+        p.nx = p.ny = p.nz = L.n;
+        p.tiles_x = L.plan.tiles_x;
+        p.tiles_y = L.plan.tiles_y;
+        p.segs = L.plan.segs;
+        p.seg_len = L.plan.seg_len;
+        p.ntiles = L.plan.ntiles;
+        p.mode = 0;
+        p.dir = 1;
+        p.weighted = 1;
+        p.omega = kMgOmega;
+        e = launch_trip_f32(L.plan.cfg, p, h->stream);
+        *cur ^= 1;
+    }
+    return e;
+}
+
+// One V-cycle on level l from a zero correction e[0]; returns the buffer
+// holding the result in *out.
+hipError_t mg_vcycle(jacobi_t* h, int l, int* out)
+{
+    const jacobi_s::MgLevel& L = h->mg[l];
+    int cur = 0;
+    if (L.n <= kMgCoarsest || l + 1 >= (int)h->mg.size()) {
+        hipError_t e = mg_smooth(h, l, &cur, kMgCoarse);
+        *out = cur;
+        return e;
+    }
+    hipError_t e = mg_smooth(h, l, &cur, kMgNu);
+    if (e == hipSuccess) e = launch_mg_residual(L.e[cur], L.rhs, L.e[1 - cur], L.n, h->stream);
+    const jacobi_s::MgLevel& C = h->mg[l + 1];
+    if (e == hipSuccess) e = launch_mg_restrict(L.e[1 - cur], L.n, C.rhs, h->stream);
+    if (e == hipSuccess)
+        e = launch_fill_f32(C.e[0], 0.f, (int64_t)(C.n + 2) * (C.n + 2) * (C.n + 2), h->stream);
+    int cc = 0;
+    if (e == hipSuccess) e = mg_vcycle(h, l + 1, &cc);
+    if (e == hipSuccess) e = launch_mg_prolong_add(C.e[cc], L.e[cur], L.n, h->stream);
+    if (e == hipSuccess) e = mg_smooth(h, l, &cur, kMgNu);
+    *out = cur;
+    return e;
+}
+
+// One outer step of the multigrid-corrected refinement: FP64 residual,
+// rhs = fl32(r 2^-s), one V-cycle from zero, u += fl64(e) 2^s.
+int outer_mg(jacobi_t* h)
+{
+    const AuxProblem& a = aux_view(h);
+    hipError_t e = launch_residual_tab(nullptr, 1, a, nullptr, a.rblocks, h->partials,
+                                       h->red_out, h->stream);
+    if (e == hipSuccess)
+        e = launch_make_rhs_tab(nullptr, 1, a, nullptr, h->red_out, h->scale_exp, h->stream);
+    if (e == hipSuccess) e = launch_zero_e_tab(nullptr, 1, a, h->stream);
+    int cur = 0;
+    if (e == hipSuccess) e = mg_vcycle(h, 0, &cur);
+    if (e == hipSuccess)
+        e = launch_apply_correction_tab(nullptr, 1, a, nullptr, cur, h->scale_exp, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "multigrid step");
+    h->sweeps += 1;
+    return JACOBI_OK;
+}
+
 // Times every candidate on real sweeps of the iterate (A/B FP64 sweeps are
 // bitwise the same for every configuration) and keeps the fastest.
 int autotune_single(jacobi_t* h, int64_t* n)
@@ -619,10 +730,30 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     h->flags = reinterpret_cast<int*>(h->ws + L.flags_off);
     h->flag_ints = L.flag_ints;
     h->done = reinterpret_cast<int*>(h->ws + L.done_off);
-    if (d->dtype == JACOBI_F32_REFINED) {
+    if (d->dtype != JACOBI_F64) {
         h->e[0] = reinterpret_cast<float*>(h->ws + L.e0_off);
         h->e[1] = reinterpret_cast<float*>(h->ws + L.e1_off);
         h->rhs = reinterpret_cast<float*>(h->ws + L.rhs_off);
+    }
+    if (d->dtype == JACOBI_F32_MULTIGRID) {
+        int64_t n = d->nx;
+        jacobi_s::MgLevel lv0{(int)n, {h->e[0], h->e[1]}, h->rhs, h->plans[kMgT]};
+        h->mg.push_back(lv0);
+        for (size_t q = 0; q < L.mg_off.size(); ++q) {
+            n = (n - 1) / 2;
+            const size_t fb = (size_t)round_up((n + 2) * (n + 2) * (n + 2) * 4, 256);
+            jacobi_s::MgLevel lv{};
+            lv.n = (int)n;
+            lv.e[0] = reinterpret_cast<float*>(h->ws + L.mg_off[q]);
+            lv.e[1] = reinterpret_cast<float*>(h->ws + L.mg_off[q] + fb);
+            lv.rhs = reinterpret_cast<float*>(h->ws + L.mg_off[q] + 2 * fb);
+            if (!make_plan(n, n, n, default_cfg(kMgT), 0, false, kCUs, &lv.plan)) {
+                delete h;
+                return fail(JACOBI_EUNSUPPORTED, "no trip plan for multigrid level n=%lld",
+                            (long long)n);
+            }
+            h->mg.push_back(lv);
+        }
     }
     h->aux.nx = (int)d->nx;
     h->aux.ny = (int)d->ny;
@@ -643,11 +774,18 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
                                 static_cast<double*>(d->grid1), h->px, h->py, nx2,
                                 ny2, nz2, h->stream);
     }
-    if (e == hipSuccess && d->dtype == JACOBI_F32_REFINED) {
+    if (e == hipSuccess && d->dtype != JACOBI_F64) {
         const int64_t box = (d->nx + 2) * (d->ny + 2) * (d->nz + 2);
         e = launch_fill_f32(h->e[0], 0.f, box, h->stream);
         if (e == hipSuccess) e = launch_fill_f32(h->e[1], 0.f, box, h->stream);
         if (e == hipSuccess) e = launch_fill_f32(h->rhs, 0.f, box, h->stream);
+        // coarse levels: zero boxes (the boundary layers stay zero for good)
+        for (size_t q = 1; q < h->mg.size() && e == hipSuccess; ++q) {
+            const int64_t nb = (int64_t)(h->mg[q].n + 2) * (h->mg[q].n + 2) * (h->mg[q].n + 2);
+            e = launch_fill_f32(h->mg[q].e[0], 0.f, nb, h->stream);
+            if (e == hipSuccess) e = launch_fill_f32(h->mg[q].e[1], 0.f, nb, h->stream);
+            if (e == hipSuccess) e = launch_fill_f32(h->mg[q].rhs, 0.f, nb, h->stream);
+        }
     }
     if (e != hipSuccess) {
         delete h;
@@ -669,6 +807,13 @@ int jacobi_sweep(jacobi_t* h, int64_t n_steps)
         n_steps > 0)
         return replay_f64(h, n_steps);
     if (h->d.dtype == JACOBI_F64) return run_f64(h, n_steps);
+    if (h->d.dtype == JACOBI_F32_MULTIGRID) {
+        for (int64_t q = 0; q < n_steps; ++q) {
+            int rc = outer_mg(h);
+            if (rc != JACOBI_OK) return rc;
+        }
+        return JACOBI_OK;
+    }
     while (n_steps > 0) {
         const int64_t m = std::min<int64_t>(h->inner, n_steps);
         int rc = outer_f32(h, m);

@@ -15,6 +15,7 @@ hipError_t trip_dispatch_f32_m0(const TripConfig&, const TripParams&, hipStream_
 hipError_t trip_dispatch_f32_m2(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f32rhs_m0(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f32rhs_m2(const TripConfig&, const TripParams&, hipStream_t);
+hipError_t trip_dispatch_f32w_m0(const TripConfig&, const TripParams&, hipStream_t);
 
 bool trip_config_supported(int dtype_f32, const TripConfig& c)
 {
@@ -44,6 +45,7 @@ hipError_t launch_trip_f32(const TripConfig& c, const TripParams& p,
                            hipStream_t s)
 {
     const bool rhs = p.rhs || p.rhs_in_table;
+    if (p.weighted) return rhs && p.mode == 0 ? trip_dispatch_f32w_m0(c, p, s) : hipErrorInvalidValue;
     switch (p.mode) {
     case 0: return rhs ? trip_dispatch_f32rhs_m0(c, p, s) : trip_dispatch_f32_m0(c, p, s);
     case 2: return rhs ? trip_dispatch_f32rhs_m2(c, p, s) : trip_dispatch_f32_m2(c, p, s);

@@ -101,7 +101,10 @@ struct Xch {
     static constexpr int nbuf = 2 * one <= 150 * 1024 ? 2 : 1;
 };
 
-template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE>
+// WT: weighted (damped) sweeps e' = e + w (v - e), v the Eq. (1) update plus
+// the right-hand side, w = p.omega (the multigrid smoother).
+template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE,
+          bool WT = false>
 __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int tile,
                                          Real (*xch)[T][W][2][64])
 {
@@ -114,6 +117,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     // is a compile-time constant (no register copies of loads in flight).
     constexpr int U = PF;
     const Real c6 = Sixth<Real>::v;
+    const Real omega = (Real)p.omega;
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -306,6 +310,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
                 Real sum = P[s][r] + xo;
                 if (RHS) sum = sum + (Real)rr[RHS ? 2 * s : 0][r];
                 e = sum * c6;
+                if (WT) e = C[s][r] + omega * (e - C[s][r]);
                 if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
             }
             P[s][r] = inpl + C[s][r];
@@ -476,7 +481,7 @@ __device__ __forceinline__ void finish_team(const TripParams& p, int tile, int t
 //         items (team, tile) from one ticket counter in team-major order,
 //         so every item an item waits for has a smaller ticket (no
 //         deadlock, whatever number of workgroups is resident).
-template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE>
+template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false>
 __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 {
     constexpr bool FLAGS = MODE == 1;
@@ -562,20 +567,20 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             wait_team(p.flags, p.done, p.err, p.tiles_x, p.tiles_y, p.segs, p.ntiles,
                       p.looseness, p.spin_limit, tile, team);
         if (interior_tile)
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, false>(p, g, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, false, WT>(p, g, tile, xch);
         else
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, true>(p, g, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, true, WT>(p, g, tile, xch);
         if (MODE == 3) finish_team(p, tile, team);
     }
 }
 
 // Launches one trip in MODE with tile shape (T, R, W).
-template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE>
+template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false>
 hipError_t launch_mode(const TripParams& p, hipStream_t s)
 {
     const dim3 block(64 * W);
     if constexpr (MODE == 0) {
-        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 0>),
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 0, WT>),
                            dim3(p.ntiles), block, 0, s, p);
         return hipGetLastError();
     }
@@ -586,24 +591,24 @@ hipError_t launch_mode(const TripParams& p, hipStream_t s)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&trip_kernel<Real, T, R, W, PF, RHS, MODE>),
+            &per_cu, reinterpret_cast<const void*>(&trip_kernel<Real, T, R, W, PF, RHS, MODE, WT>),
             64 * W, 0);
     if (e != hipSuccess) return e;
     int grid = cus * (per_cu > 0 ? per_cu : 1);
     const int64_t items = MODE == 3 ? (int64_t)p.ntiles * p.teams : p.ntiles;
     if (grid > items) grid = (int)items;
-    hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE>), dim3(grid), block,
+    hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE, WT>), dim3(grid), block,
                        0, s, p);
     return hipGetLastError();
 }
 
 // Launches the compiled tile shape `c` of one precision, rhs flag and mode.
-template <typename Real, bool RHS, int MODE>
+template <typename Real, bool RHS, int MODE, bool WT = false>
 hipError_t dispatch_unit(const TripConfig& c, const TripParams& p, hipStream_t s)
 {
 #define JACOBI_CASE(T_, R_, W_)                     \
     if (c.T == T_ && c.R == R_ && c.W == W_)        \
-        return launch_mode<Real, T_, R_, W_, kPrefetch, RHS, MODE>(p, s);
+        return launch_mode<Real, T_, R_, W_, kPrefetch, RHS, MODE, WT>(p, s);
     JACOBI_TRIP_CFGS(JACOBI_CASE)
 #undef JACOBI_CASE
     return hipErrorInvalidValue;

@@ -58,7 +58,8 @@ class Jacobi:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         d = JacobiDesc()
         d.nx, d.ny, d.nz = self.nx, self.ny, self.nz
-        d.dtype = _lib.F64 if dtype == "f64" else _lib.F32_REFINED
+        d.dtype = {"f64": _lib.F64, "f32_refined": _lib.F32_REFINED,
+                   "f32_multigrid": _lib.F32_MULTIGRID}[dtype]
         d.layout = _lib.LAYOUT_AB if layout == "ab" else _lib.LAYOUT_COMPRESSED
         d.t = t
         d.tile_rows = tile_rows

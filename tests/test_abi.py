@@ -149,3 +149,14 @@ def test_tile_menu():
     assert tile_supported(4, 32, 4)
     assert not tile_supported(4, 24, 4)
     assert not tile_supported(9, 32, 4)
+
+
+def test_multigrid_shape_errors():
+    """The multigrid dtype needs the A/B layout and an n^3 interior with
+    n = 2^k - 1; other shapes are rejected before anything is allocated."""
+    from paper_1006_3148_amd import lib
+    n = ctypes.c_size_t()
+    for dims, layout, rc in (((31, 31, 31), 0, 0), ((32, 32, 32), 0, -2),
+                             ((31, 31, 15), 0, -2), ((31, 31, 31), 1, -2)):
+        d = _desc(dims=dims, dtype=2, layout=layout)
+        assert lib.jacobi_workspace_size(ctypes.byref(d), ctypes.byref(n)) == rc, dims
