@@ -46,7 +46,7 @@ def parse():
                     help="only measure the multigrid-corrected time to 1e-8 at N^3 "
                          "(N = 2^k - 1)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=40.0)
     ap.add_argument("--quick", action="store_true",
                     help="skip the batched / 1024^3 / time-to-tolerance extras")
     ap.add_argument("--probe", action="store_true",
@@ -276,10 +276,13 @@ def main():
         extra["glups_by_layout_t_512"] = tab
         if not args.quick:
             extra["n64_100_sweeps"] = bench_small_64(torch)
-            extra["n1024_compressed"] = bench_1024(torch, t)
+            extra["n1024"] = bench_1024(torch, t)
+            extra["teams_512"] = bench_teams(torch)
+            extra["multigrid_time_to_1e-8_511"] = bench_multigrid_tts(torch, 511)
             extra["batched_256"] = bench_batched(torch)
             extra["time_to_1e-8_256"] = bench_time_to_tol(torch, 256, t)
-            extra["time_to_1e-8_512"] = "profiles/time_to_tol_512.json (bench.py --tts-only 512)"
+            extra["time_to_1e-8_512_1024"] = ("profiles/time_to_tol_512.json, "
+                                              "profiles/time_to_tol_1024.json (bench.py --tts-only N)")
         out["extra"] = extra
 
     if not args.no_cpu:
@@ -287,26 +290,62 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_1024(torch, t, sweeps=48):
-    """Compressed single grid at 1024^3 (8.6 GB + shift planes): GLUP/s."""
+def bench_1024(torch, t, sweeps=50):
+    """1024^3 interior, sine-mode faces: the compressed single grid (8.6 GB
+    plus shift planes) and the A/B layout (17.2 GB), GLUP/s of `sweeps`
+    sweeps after a warm-up trip."""
     import synth
     from paper_1006_3148_amd import Jacobi
-    box = synth.sine_face_box(1024, 1024, 1024, seed=3)
-    j = Jacobi(box, t=t, layout="compressed")
+    box = torch.from_numpy(synth.sine_face_box(1024, 1024, 1024, seed=3)).cuda()
+    out = {"sweeps": sweeps, "t": t}
+    for layout in ("compressed", "ab"):
+        j = Jacobi(box, t=t, layout=layout)
+        j.sweep(2 * t)
+        j.sync()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        j.sweep(sweeps)
+        j.sync()
+        dt = time.perf_counter() - a
+        info = j.info()
+        j.close()
+        del j
+        torch.cuda.empty_cache()
+        g = 1024 ** 3 * sweeps / dt / 1e9
+        out[layout] = {"seg_len": info["seg_len"], "glups": round(g, 1),
+                       "roofline_frac_spec": round(g / (HBM_PEAK_GBS * t / 16.0), 4)}
     del box
-    j.sweep(2 * t)
-    j.sync()
-    torch.cuda.synchronize()
-    a = time.perf_counter()
-    j.sweep(sweeps)
-    j.sync()
-    dt = time.perf_counter() - a
-    info = j.info()
-    j.close()
     torch.cuda.empty_cache()
-    return {"sweeps": sweeps, "t": t, "seg_len": info["seg_len"],
-            "glups": round(1024 ** 3 * sweeps / dt / 1e9, 1),
-            "roofline_frac_spec": round(1024 ** 3 * sweeps / dt / 1e9 / (HBM_PEAK_GBS * t / 16.0), 4)}
+    return out
+
+
+def bench_teams(torch, n=512, sweeps=200):
+    """Trips in one persistent launch (teams, per-tile counters, looseness
+    d_u) against one launch per trip, and 16 sweeps per launch as two
+    chained teams of t=8."""
+    import synth
+    from paper_1006_3148_amd import Jacobi
+    box = torch.from_numpy(synth.uniform_box(n, n, n, seed=2)).cuda()
+    out = {"n": n, "sweeps": sweeps}
+    for name, kw in (("kernel_boundaries_t5", dict(t=5)),
+                     ("teams40_t5_relaxed", dict(t=5, teams=40, looseness=-1)),
+                     ("teams40_t5_lockstep", dict(t=5, teams=40, looseness=0)),
+                     ("teams40_t5_du2", dict(t=5, teams=40, looseness=2)),
+                     ("kernel_boundaries_t8", dict(t=8)),
+                     ("t16_as_2_teams_of_8", dict(t=8, teams=2, looseness=-1))):
+        j = Jacobi(box, **kw)
+        j.sweep(sweeps)
+        j.sync()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        j.sweep(sweeps)
+        j.sync()
+        dt = time.perf_counter() - a
+        j.close()
+        out[name] = round(n ** 3 * sweeps / dt / 1e9, 1)
+    del box
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batched(torch, count=256, seed=4, sweeps=500):

@@ -134,6 +134,12 @@ hipError_t launch_mg_residual(const float* e, const float* rhs, float* r, int n,
 hipError_t launch_mg_restrict(const float* r, int n, float* rc, hipStream_t s);
 hipError_t launch_mg_prolong_add(const float* ec, float* e, int n, hipStream_t s);
 
+// One FP64 sweep of a small A/B box, one thread per interior cell (the
+// boundary layers of both grids already hold the boundary).
+hipError_t launch_sweep1_f64(const double* a, double* b, int64_t px, int64_t py, int nx,
+                             int ny, int nz, hipStream_t s);
+constexpr int64_t kSmallBoxCells = 128 * 128 * 128;
+
 // Bandwidth probes: STREAM-like copy b[i] = a[i] and in-place update
 // a[i] += 1.0 (the paper's array-update benchmark).
 hipError_t launch_stream_copy(const double* a, double* b, int64_t n,

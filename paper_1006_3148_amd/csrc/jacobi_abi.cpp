@@ -377,6 +377,11 @@ int run_f64(jacobi_t* h, int64_t n)
             e = launch_trip(h, h->t, false, grid_origin(h, h->cur),
                             grid_origin(h, 1 - h->cur), nullptr, h->px, h->py, 3, 1, k);
             h->cur ^= (k & 1);
+        } else if (h->d.layout == JACOBI_LAYOUT_AB && L == 1 &&
+                   h->d.nx * h->d.ny * h->d.nz <= kSmallBoxCells) {
+            e = launch_sweep1_f64(grid_origin(h, h->cur), grid_origin(h, 1 - h->cur), h->px,
+                                  h->py, (int)h->d.nx, (int)h->d.ny, (int)h->d.nz, h->run);
+            h->cur ^= 1;
         } else if (h->d.layout == JACOBI_LAYOUT_AB) {
             e = launch_trip(h, L, false, grid_origin(h, h->cur),
                             grid_origin(h, 1 - h->cur), nullptr, h->px, h->py,

@@ -307,6 +307,27 @@ __global__ __launch_bounds__(256) void stream_update_kernel(dv2* __restrict__ a,
     }
 }
 
+// One Jacobi sweep (Eq. (1)) of the interior, one thread per cell, for boxes
+// small enough to sit in the caches: the k-streaming trip kernel needs a
+// pipeline of several dependent steps per tile, while here a sweep is one
+// round of independent loads.  Same fold order, times fl(1/6).
+__global__ __launch_bounds__(256) void sweep1_kernel(const double* __restrict__ a,
+                                                     double* __restrict__ b, int64_t px,
+                                                     int64_t py, int nx, int ny, int nz)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6) + 1;
+    const int k = blockIdx.z + 1;
+    if (i > nx || j > ny || k > nz) return;
+    const int64_t c = (int64_t)k * py + (int64_t)j * px + i;
+    double s = a[c - 1] + a[c + 1];
+    s = s + a[c - px];
+    s = s + a[c + px];
+    s = s + a[c - py];
+    s = s + a[c + py];
+    b[c] = s * (1.0 / 6.0);
+}
+
 int grid_for_elems(int64_t n)
 {
     int64_t g = (n + 255) / 256;
@@ -420,6 +441,14 @@ hipError_t launch_copy_box_f64(const double* src, int64_t spx, int64_t spy,
     hipLaunchKernelGGL(copy_box_kernel,
                        dim3((int)((int64_t)ny2 * nz2 < 65536 ? (int64_t)ny2 * nz2 : 65536)), dim3(256), 0, s,
                        src, spx, spy, dst, dpx, dpy, nx2, ny2, nz2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep1_f64(const double* a, double* b, int64_t px, int64_t py, int nx,
+                             int ny, int nz, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep1_kernel, dim3((nx + 63) / 64, (ny + 3) / 4, nz), dim3(256), 0, s,
+                       a, b, px, py, nx, ny, nz);
     return hipGetLastError();
 }
 
