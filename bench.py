@@ -620,7 +620,8 @@ def bench_multigrid_tts(torch, n, rel_tol=1e-8):
 def _kernel_hash():
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels_trip.hip", "trip_device.h"):
+    for name in ("trip_kernel.h", "trip_device.h", "trip_configs.h", "internal.h",
+                 "kernels_trip.hip", "trip_f64_m0.hip", "trip_f64_m1.hip"):
         with open(os.path.join(ROOT, "paper_1006_3148_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
