@@ -13,7 +13,8 @@
  *     box is a fixed Dirichlet boundary (the boundary value problem).
  *   - Sect. 2.1: temporal blocking -- t sweeps are applied per trip through
  *     memory; the optional "compressed grid" keeps a single grid and stores
- *     each trip's result shifted by (-t,-t,-t) and (+t,+t,+t) alternately.
+ *     each trip's result shifted by (-t,-t,-t) or (+t,+t,+t) (here with E
+ *     extra planes along k, see jacobi_grid_bytes).
  *   - Sect. 2.2, Eq. (3): relaxed synchronization through per-worker progress
  *     counters instead of global barriers.
  *
@@ -87,7 +88,9 @@ typedef struct {
     int32_t tile_rows;   /* j-rows per tile: 0 = default for t, else one of
                             the compiled shapes (jacobi_tile_supported) */
     int32_t rows_per_wave; /* 0 = default; with tile_rows selects the shape */
-    int32_t seg_len;     /* k planes per tile segment, 0 = automatic */
+    int32_t seg_len;     /* k planes per tile segment, 0 = automatic;
+                            COMPRESSED needs >= 2t, and caps E (below) at
+                            seg_len - 2t */
     int32_t inner_sweeps;/* JACOBI_F32_REFINED: FP32 sweeps per outer
                             correction step (0 = 32) */
     int32_t use_graph;   /* 1: A/B FP64 jacobi_sweep calls are captured once
@@ -113,10 +116,16 @@ typedef struct {
 
 typedef struct jacobi_s jacobi_t;
 
-/* Bytes each grid buffer must hold for `d` (dims, layout and t are read).
- * AB: (nx+2)(ny+2)(nz+2) doubles.  COMPRESSED: the box plus 2t shift planes
- * per axis, (nx+2+2t)(ny+2+2t)(nz+2+2t) doubles (2t, not t, so that a trip of
- * any length <= t fits from every shift offset).  Errors: JACOBI_EINVAL. */
+/* Bytes each grid buffer must hold for `d` (dims, layout, t and seg_len are
+ * read).  AB: (nx+2)(ny+2)(nz+2) doubles.  COMPRESSED: the box plus 2t shift
+ * planes in i and j and 2t+2E in k, (nx+2+2t)(ny+2+2t)(nz+2+2t+2E) doubles
+ * (2t, not t, so that a trip of any length <= t fits from every shift
+ * offset).  A trip of L sweeps shifts by L in i and j and by L+E in k, with
+ * E = 2t for t <= 5 (at most seg_len - 2t when seg_len is set) and E = 0 for
+ * t > 5: the extra k shift lets a tile run up to E steps behind its
+ * neighbours before they wait for it.  JACOBI_KREV and JACOBI_ZEXTRA (see
+ * jacobi_create) change E and must be the same here and there.
+ * Errors: JACOBI_EINVAL. */
 int jacobi_grid_bytes(const jacobi_desc *d, size_t *bytes);
 
 /* Bytes of device workspace `d` needs (flags, reduction partials, and for
@@ -131,7 +140,14 @@ int jacobi_workspace_size(const jacobi_desc *d, size_t *bytes);
  * May launch set-up kernels on the stream (AB: copies the box into grid1 so
  * both grids carry the boundary).  Errors: JACOBI_EINVAL (null pointers,
  * dims < 1 or > 2^20, misaligned buffers), JACOBI_EUNSUPPORTED (t or tile
- * shape not compiled), JACOBI_EWORKSPACE, JACOBI_EHIP. */
+ * shape not compiled), JACOBI_EWORKSPACE, JACOBI_EHIP.
+ * Environment, read here (diagnostics; results are the same bits):
+ *   JACOBI_SPIN_LIMIT=n   bound on a compressed tile's waits (then
+ *                         JACOBI_ETIMEOUT);
+ *   JACOBI_XCD_ORDER=0    compressed trips take tiles from one ticket counter
+ *                         instead of per-XCD claim groups;
+ *   JACOBI_KREV=0         backward compressed trips stream k upwards (E = 0);
+ *   JACOBI_ZEXTRA=planes  the extra k shift E of compressed trips. */
 int jacobi_create(const jacobi_desc *d, jacobi_t **out);
 
 /* Applies n_steps Jacobi sweeps (JACOBI_F32_REFINED: n_steps FP32 inner

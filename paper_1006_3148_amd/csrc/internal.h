@@ -53,7 +53,19 @@ struct TripParams {
     int weighted;               // FP32 with rhs: weighted sweeps (multigrid
                                 // smoother) with weight omega
     float omega;
+    int groups;                 // mode 1: per-XCD claim groups (> 1) or one
+                                // ticket counter (1)
+    int chunk;                  // mode 1 groups: tiles per chunk (set at launch)
+    int* gcnt;                  // mode 1 groups: kClaimGroups counters, stride
+                                // kFlagStride ints (zeroed)
+    int zshift;                 // mode 1: k shift of dst against src
+                                // (planes, >= T)
+    int krev;                   // mode 1, dir -1: src/dst are k-mirrored
+                                // views (origin at plane nz+1, py < 0)
 };
+
+// Claim groups of a compressed-grid launch (one per XCD).
+constexpr int kClaimGroups = 8;
 
 constexpr int kFlagStride = 32;  // ints per flag (128 B line each)
 

@@ -63,7 +63,7 @@ TripConfig default_cfg(int T, bool compressed)
 }
 
 bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
-               int seg_req, bool compressed, int target_tiles, Plan* out)
+               int seg_req, bool compressed, int target_tiles, Plan* out, int min_seg)
 {
     const int T = cfg.T;
     const int OX = 64 - 2 * T;
@@ -77,7 +77,7 @@ bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
     const int64_t nz2 = nz + 2;
     const int64_t plane_tiles = (int64_t)p.tiles_x * p.tiles_y;
     if (seg_req > 0) {
-        if (compressed && seg_req < 2 * T) return false;
+        if (compressed && seg_req < std::max(2 * T, min_seg)) return false;
         p.seg_len = (int)std::min<int64_t>(seg_req, nz2);
     } else {
         // Minimise (rounds of concurrent tiles) x (steps of one tile): a tile
@@ -86,7 +86,7 @@ bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
         const int conc = target_tiles > 0 ? target_tiles : kCUs;
         double best = 1e300;
         int best_len = (int)nz2;
-        const int min_len = std::max(compressed ? 2 * T : 1, 4 * T);
+        const int min_len = std::max(compressed ? std::max(2 * T, min_seg) : 1, 4 * T);
         for (int64_t segs = 1; segs <= 256; ++segs) {
             const int64_t len = (nz2 + segs - 1) / segs;
             if (len < min_len && segs > 1) break;
@@ -115,8 +115,11 @@ struct jacobi_s {
     jacobi_desc d{};
     int t = 4;
     int64_t px = 0, py = 0;  // storage pitches of the FP64 grid(s)
-    int room = 0;            // compressed: shift room per axis (2t)
-    int off = 0;             // compressed: current origin offset per axis
+    int room = 0;            // compressed: shift room in i and j (2t)
+    int off = 0;             // compressed: current origin offset in i and j
+    int zextra = 0;          // compressed: extra k shift per trip (E)
+    int roomz = 0;           // compressed: shift room in k (2t + 2E)
+    int offz = 0;            // compressed: current origin offset in k
     int cur = 0;             // AB: grid holding the current iterate
     hipStream_t stream = nullptr;
     int tile_rows = 0, rpw = 0, seg_req = 0;
@@ -140,8 +143,13 @@ struct jacobi_s {
     int* scale_exp = nullptr;
     double* red_out = nullptr;
     double* partials = nullptr;
+    int* gcnt = nullptr;     // claim-group counters (compressed trips)
     int* flags = nullptr;
     int64_t flag_ints = 0;
+    // compressed trips claim tiles in per-XCD groups; JACOBI_XCD_ORDER=0
+    // falls back to one ticket counter
+    bool xcd_order = true;
+    bool krev = false;  // backward compressed trips use the k-mirrored view
     int* done = nullptr;     // per-team finished-tile counts (teams >= 2)
     float* e[2] = {nullptr, nullptr};
     float* rhs = nullptr;
@@ -202,6 +210,36 @@ constexpr int kTuneDefaultT = 5;
 
 constexpr int kMaxTeams = 1024;
 
+// Extra shift along k of a compressed trip (planes).  A forward trip of L
+// sweeps stores its result shifted by (-L, -L, -L-E) (a backward trip by
+// (+L, +L, +L+E)): a tile then overwrites a storage plane 3L+E steps after
+// the tiles it shares it with started reading it, instead of 3L, which lets
+// tiles that started a little later than their neighbours run without
+// waiting.  A segment of the k split must hold 2L+E planes, so an explicit
+// segment length caps E.
+// Backward compressed trips stream k downwards (a k-mirrored view of the
+// grid) for t <= kKrevMaxT; the mirrored kernel holds one more plane per
+// stage, which no longer fits in registers for larger t.  JACOBI_KREV=0
+// streams them upwards like forward trips.
+constexpr int kKrevMaxT = 5;
+bool compressed_krev(int t)
+{
+    if (const char* s = std::getenv("JACOBI_KREV"))
+        if (std::atoi(s) == 0) return false;
+    return t <= kKrevMaxT;
+}
+
+int compressed_zextra(const jacobi_desc* d, int t)
+{
+    // a trip streaming upwards with a +k shift stores ahead of its stream:
+    // no extra shift unless every backward trip is mirrored
+    if (!compressed_krev(t)) return 0;
+    int E = 2 * t;
+    if (const char* s = std::getenv("JACOBI_ZEXTRA")) E = std::max(0, std::atoi(s));
+    if (d->seg_len > 0) E = std::max(0, std::min(E, d->seg_len - 2 * t));
+    return E;
+}
+
 int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                       Layout* lay)
 {
@@ -238,6 +276,7 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     if (d->seg_len < 0) return fail(JACOBI_EINVAL, "seg_len < 0");
     const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
     const int room = comp ? 2 * t : 0;
+    const int zextra = comp ? compressed_zextra(d, t) : 0;
     const int64_t plane_bytes = (d->nx + 2 + room) * (d->ny + 2 + room) * 8;
     if (plane_bytes >= ((int64_t)1 << 31))
         return fail(JACOBI_EINVAL, "one k-plane must be < 2 GiB");
@@ -256,7 +295,7 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                         "tile shape t=%d rows=%d rows_per_wave=%d is not compiled",
                         T, cfg.R * cfg.W, cfg.R);
         if (!make_plan(d->nx, d->ny, d->nz, cfg, T == t ? d->seg_len : 0, comp,
-                       kCUs, &plans[T]))
+                       kCUs, &plans[T], comp ? 2 * T + zextra : 0))
             return fail(JACOBI_EUNSUPPORTED,
                         "tile shape t=%d rows=%d cannot cover this box%s", T,
                         cfg.R * cfg.W,
@@ -281,7 +320,8 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     L.partials_off = 256;
     L.flags_off = (size_t)round_up(L.partials_off + 2 * (int64_t)nb * sizeof(double), 256);
     const bool teams = d->teams > 1;
-    L.flag_ints = (comp || teams) ? max_tiles * kFlagStride : 0;
+    // claim-group counters, then one progress word per tile
+    L.flag_ints = (comp || teams) ? (max_tiles + kClaimGroups) * kFlagStride : 0;
     L.done_off = (size_t)round_up(L.flags_off + L.flag_ints * sizeof(int), 256);
     size_t end = L.done_off + (teams ? (size_t)d->teams * kFlagStride * sizeof(int) : 0);
     L.e0_off = L.e1_off = L.rhs_off = 0;
@@ -310,7 +350,7 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
 
 hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
                        const float* rhs, int64_t px, int64_t py, int mode,
-                       int dir, int teams = 1)
+                       int dir, int teams = 1, int zshift = 0, bool krev = false)
 {
     const Plan& pl = h->plans[T];
     TripParams p{};
@@ -333,14 +373,18 @@ hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
     p.dir = dir;
     p.flags = h->flags;
     p.ticket = h->ticket;
+    p.groups = h->xcd_order ? kClaimGroups : 1;
+    p.gcnt = h->gcnt;
+    p.zshift = zshift > 0 ? zshift : T;
+    p.krev = krev ? 1 : 0;
     p.err = h->err;
     p.spin_limit = h->spin_limit;
     p.teams = teams;
     p.looseness = h->d.looseness;
     p.done = h->done;
     if (mode == 1 || mode == 3) {
-        hipError_t e = launch_fill_i32(h->flags, 0, (int64_t)pl.ntiles * kFlagStride,
-                                       h->run);
+        hipError_t e = launch_fill_i32(h->gcnt, 0,
+                                       (int64_t)(kClaimGroups + pl.ntiles) * kFlagStride, h->run);
         if (e == hipSuccess && mode == 3)
             e = launch_fill_i32(h->done, 0, (int64_t)teams * kFlagStride, h->run);
         if (e == hipSuccess) e = launch_fill_i32(h->ticket, 0, 1, h->run);
@@ -350,18 +394,49 @@ hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
                : launch_trip_f64(pl.cfg, p, h->run);
 }
 
-double* grid_origin(jacobi_t* h, int which_off)
+// A/B: cell (0,0,0) of grid `which`.
+double* grid_origin(jacobi_t* h, int which)
 {
-    double* base = static_cast<double*>(h->d.grid0);
-    if (h->d.layout == JACOBI_LAYOUT_AB)
-        return static_cast<double*>(which_off == 0 ? h->d.grid0 : h->d.grid1);
-    return base + (int64_t)which_off * (1 + h->px + h->py);
+    return static_cast<double*>(which == 0 ? h->d.grid0 : h->d.grid1);
+}
+
+// Compressed: cell (0,0,0) of the frame at offsets (off, off, offz).
+double* comp_origin(jacobi_t* h, int off, int offz)
+{
+    return static_cast<double*>(h->d.grid0) + off * (1 + h->px) + (int64_t)offz * h->py;
 }
 
 double* current_origin(jacobi_t* h)
 {
     if (h->d.layout == JACOBI_LAYOUT_AB) return grid_origin(h, h->cur);
-    return grid_origin(h, h->off);
+    return comp_origin(h, h->off, h->offz);
+}
+
+// Direction (+1 forward: offsets decrease) and length of the next compressed
+// trip of at most L sweeps.  A trip must keep both offsets in range: i and j
+// move by L in [0, room], k by L+E in [0, roomz].  Forward trips lower
+// offz - off by E and backward trips raise it, so the direction that moves it
+// back towards E is tried first; if neither fits L, the trip is shortened
+// (results do not depend on how sweeps are split into trips).
+int comp_next_trip(const jacobi_t* h, int* L)
+{
+    const int E = h->zextra;
+    auto fits = [&](int dir, int len) {
+        return dir > 0 ? h->off >= len && h->offz >= len + E
+                       : h->room - h->off >= len && h->roomz - h->offz >= len + E;
+    };
+    const int first = h->offz - h->off < E ? -1 : 1;
+    if (fits(first, *L)) return first;
+    if (fits(-first, *L)) return -first;
+    for (int dir : {first, -first}) {
+        const int len = dir > 0 ? std::min(h->off, h->offz - E)
+                                : std::min(h->room - h->off, h->roomz - h->offz - E);
+        if (len >= 1) {
+            *L = std::min(*L, len);
+            return dir;
+        }
+    }
+    return 0;  // unreachable: room = 2t keeps one direction open
 }
 
 // n FP64 sweeps of the u grid(s).
@@ -388,19 +463,23 @@ int run_f64(jacobi_t* h, int64_t n)
                             0, 1);
             h->cur ^= 1;
         } else {
-            int dir;
-            if (h->off >= L) {
-                dir = 1;
-            } else if (h->room - h->off >= L) {
-                dir = -1;
-            } else {
-                L = h->off;  // move back to offset 0 first
-                dir = 1;
-            }
+            const int dir = comp_next_trip(h, &L);
+            if (dir == 0) return fail(JACOBI_ESTATE, "no room for a compressed trip");
             const int noff = h->off - dir * L;
-            e = launch_trip(h, L, false, grid_origin(h, h->off),
-                            grid_origin(h, noff), nullptr, h->px, h->py, 1, dir);
+            const int noffz = h->offz - dir * (L + h->zextra);
+            if (dir < 0 && h->krev) {
+                // k-mirrored view: origin at plane nz+1, negative pitch
+                const int64_t top = (h->d.nz + 1) * h->py;
+                e = launch_trip(h, L, false, comp_origin(h, h->off, h->offz) + top,
+                                comp_origin(h, noff, noffz) + top, nullptr, h->px, -h->py, 1,
+                                dir, 1, L + h->zextra, true);
+            } else {
+                e = launch_trip(h, L, false, comp_origin(h, h->off, h->offz),
+                                comp_origin(h, noff, noffz), nullptr, h->px, h->py, 1, dir,
+                                1, L + h->zextra);
+            }
             h->off = noff;
+            h->offz = noffz;
         }
         if (e != hipSuccess) return hip_fail(e, "trip launch");
         n -= L;
@@ -661,11 +740,13 @@ int jacobi_grid_bytes(const jacobi_desc* d, size_t* bytes)
     if (d->nx < 1 || d->ny < 1 || d->nz < 1)
         return fail(JACOBI_EINVAL, "interior dims must be >= 1");
     const int t = d->t == 0 ? 4 : d->t;
-    // Compressed: 2t planes of shift room per axis, so that a trip of any
+    // Compressed: 2t planes of shift room in i and j, so that a trip of any
     // length <= t fits in one direction from every offset (no split trips
-    // when sweep counts are not multiples of t).
-    const int room = d->layout == JACOBI_LAYOUT_COMPRESSED ? 2 * t : 0;
-    *bytes = (size_t)((d->nx + 2 + room) * (d->ny + 2 + room) * (d->nz + 2 + room) * 8);
+    // when sweep counts are not multiples of t), and 2t + 2E in k.
+    const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
+    const int room = comp ? 2 * t : 0;
+    const int roomz = comp ? room + 2 * compressed_zextra(d, t) : 0;
+    *bytes = (size_t)((d->nx + 2 + room) * (d->ny + 2 + room) * (d->nz + 2 + roomz) * 8);
     return JACOBI_OK;
 }
 
@@ -717,6 +798,9 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
     h->room = comp ? 2 * t : 0;
     h->off = h->room;
+    h->zextra = comp ? compressed_zextra(d, t) : 0;
+    h->roomz = h->room + 2 * h->zextra;
+    h->offz = h->roomz;
     h->px = d->nx + 2 + h->room;
     h->py = h->px * (d->ny + 2 + h->room);
     h->stream = static_cast<hipStream_t>(d->stream);
@@ -732,7 +816,10 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     h->scale_exp = h->ticket + 2;
     h->red_out = reinterpret_cast<double*>(h->ws + 64);
     h->partials = reinterpret_cast<double*>(h->ws + L.partials_off);
-    h->flags = reinterpret_cast<int*>(h->ws + L.flags_off);
+    h->gcnt = reinterpret_cast<int*>(h->ws + L.flags_off);
+    h->flags = h->gcnt + kClaimGroups * kFlagStride;
+    if (const char* s = std::getenv("JACOBI_XCD_ORDER")) h->xcd_order = std::atoi(s) != 0;
+    h->krev = compressed_krev(t);
     h->flag_ints = L.flag_ints;
     h->done = reinterpret_cast<int*>(h->ws + L.done_off);
     if (d->dtype != JACOBI_F64) {

@@ -9,6 +9,7 @@ namespace jacobi_impl {
 
 hipError_t trip_dispatch_f64_m0(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f64_m1(const TripConfig&, const TripParams&, hipStream_t);
+hipError_t trip_dispatch_f64_m1r(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f64_m2(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f64_m3(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f32_m0(const TripConfig&, const TripParams&, hipStream_t);
@@ -32,7 +33,7 @@ hipError_t launch_trip_f64(const TripConfig& c, const TripParams& p,
 {
     switch (p.mode) {
     case 0: return trip_dispatch_f64_m0(c, p, s);
-    case 1: return trip_dispatch_f64_m1(c, p, s);
+    case 1: return p.krev ? trip_dispatch_f64_m1r(c, p, s) : trip_dispatch_f64_m1(c, p, s);
     case 2: return trip_dispatch_f64_m2(c, p, s);
     case 3: return trip_dispatch_f64_m3(c, p, s);
     default: return hipErrorInvalidValue;

@@ -28,11 +28,12 @@ TripConfig default_cfg(int T, bool compressed = false);
 
 // Tiling of one (nx, ny, nz) box for `cfg`.  seg_req > 0 fixes the k segment
 // length; `compressed` enforces tiles and segments >= 2T (the shift safety
-// condition of the compressed grid).  `target_tiles` is the tile count the
-// segment heuristic aims to fill (concurrent workgroups).  False if the shape
-// cannot cover the box.
+// condition of the compressed grid) and segments >= min_seg.  `target_tiles`
+// is the tile count the segment heuristic aims to fill (concurrent
+// workgroups).  False if the shape cannot cover the box.
 bool make_plan(int64_t nx, int64_t ny, int64_t nz, const TripConfig& cfg,
-               int seg_req, bool compressed, int target_tiles, Plan* out);
+               int seg_req, bool compressed, int target_tiles, Plan* out,
+               int min_seg = 0);
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 

@@ -73,6 +73,26 @@ __device__ __forceinline__ void flag_store(int* f, int v)
 
 constexpr int kDone = 0x7fffffff;
 
+// Tile claim of the compressed-grid launch with per-XCD groups.  The tile
+// order O of a forward trip (row-major: segment, row, column; a backward trip
+// mirrors the index) is cut into chunks of `chunk` consecutive tiles (the
+// workgroups one XCD holds), and chunk c belongs to group c mod 8: at any time
+// the eight XCDs work on eight consecutive chunks, each on a run of whole tile
+// rows as in the A/B map, so the ghost cells of neighbouring tiles are shared
+// in that XCD's L2 and the memory streams stay row-long.  A workgroup on XCD
+// x (workgroup b is dispatched to XCD b mod 8) takes the next tile of group x
+// with one atomic add.  Every tile waits only for tiles earlier in O; a group
+// hands out its tiles in O order, so the earliest unfinished tile is claimed
+// as soon as a workgroup of its group is free, and its dependees are done:
+// the launch completes once every group has a workgroup resident.  Returns
+// the tile in O numbering, or ntiles when the group is exhausted.
+__device__ __forceinline__ int claim_grouped(int* gcnt, int xcd, int chunk, int ntiles)
+{
+    const int k = atomicAdd(gcnt + xcd * kFlagStride, 1);
+    const int64_t v = ((int64_t)(k / chunk) * kClaimGroups + xcd) * chunk + k % chunk;
+    return v < ntiles ? (int)v : ntiles;
+}
+
 // Planes in flight per tile (register ring depth).
 #ifndef JACOBI_PREFETCH
 #define JACOBI_PREFETCH 2

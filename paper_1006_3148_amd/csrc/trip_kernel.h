@@ -36,14 +36,17 @@
 //  * boundary-layer cells pass through unchanged (Dirichlet boundary).
 //
 // Compressed grid (Sect. 2.1): with mode 1 src and dst are the same storage
-// and dst is src shifted by (-T,-T,-T) (dir=+1) or (+T,+T,+T) (dir=-1), the
-// paper's per-update shift vector times T.  A cell may only be overwritten
-// after every tile that reads it has loaded it.  Tiles are taken from a ticket
-// counter in an order in which every such reader has a smaller ticket, and a
-// tile spins on the readers' progress words before each store: the first
-// condition of Eq. (3) (Sect. 2.2) with per-tile counters instead of
-// per-thread ones.  A bounded spin turns a lost tile into an error word
-// instead of a hang.
+// and dst is src shifted by (-T,-T,-T-E) (dir=+1) or (+T,+T,+T+E) (dir=-1):
+// the paper's per-update shift vector times T, plus E extra planes along the
+// streaming axis (p.zshift = T+E), which give a tile E more steps of slack
+// before it overwrites planes its neighbours still read.  A cell may only be
+// overwritten after every tile that reads it has loaded it.  Tiles are
+// claimed in an order in which every such reader comes first (one ticket
+// counter, or the per-XCD claim groups of claim_grouped, which keep
+// neighbouring tiles on one XCD's L2), and a tile spins on the readers'
+// progress words before each store: the first condition of Eq. (3)
+// (Sect. 2.2) with per-tile counters instead of per-thread ones.  A bounded
+// spin turns a lost tile into an error word instead of a hang.
 //
 // Compiled with -ffp-contract=off: no fused multiply-add, so results are
 // bitwise equal to the plain definition.
@@ -103,8 +106,13 @@ struct Xch {
 
 // WT: weighted (damped) sweeps e' = e + w (v - e), v the Eq. (1) update plus
 // the right-hand side, w = p.omega (the multigrid smoother).
+// KREV: the tile streams a k-mirrored view of the grid (origin at the top
+// plane, negative plane pitch), used by backward compressed trips so that
+// their stores, like a forward trip's, land behind the stream.  Logical plane
+// q+1 is then physical k-1, and the update keeps Eq. (1)'s order (k-1 before
+// k+1) by holding one more plane per stage.
 template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE,
-          bool WT = false>
+          bool WT = false, bool KREV = false>
 __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int tile,
                                          Real (*xch)[T][W][2][64])
 {
@@ -172,9 +180,10 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     if (FLAGS && lane < 7) {
         const int d = lane + 1;  // bits (dx, dy, dz) of the neighbour offset
         const int sgn = p.dir > 0 ? -1 : 1;
+        const int zsgn = KREV ? -1 : sgn;
         const int ntx = tx + ((d & 1) ? sgn : 0);
         const int nty = ty + ((d & 2) ? sgn : 0);
-        const int nsg = seg + ((d & 4) ? sgn : 0);
+        const int nsg = seg + ((d & 4) ? zsgn : 0);
         if (ntx >= 0 && ntx < g.tiles_x && nty >= 0 && nty < g.tiles_y &&
             nsg >= 0 && nsg < g.segs)
             dep = (nsg * g.tiles_y + nty) * g.tiles_x + ntx;
@@ -188,7 +197,8 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     // produced by stage s in the previous step); X[T]: the plane stage T
     // completed.  P, C: per-stage k-streaming state (partial sum, and the
     // plane consumed in the previous step).
-    Real X[T + 1][R], P[T][R], C[T][R];
+    // KREV: P holds the in-plane sum alone and D the plane before C.
+    Real X[T + 1][R], P[T][R], C[T][R], D[KREV ? T : 1][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -197,6 +207,7 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
         for (int s = 0; s < T; ++s) {
             P[s][r] = Real(0);
             C[s][r] = Real(0);
+            if (KREV) D[KREV ? s : 0][r] = Real(0);
         }
     }
     // rr[m]: rhs plane a+n-1-m; stage s+1 completes plane a+n-2s-1 and takes
@@ -221,8 +232,8 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
         soff[r] = (lane_out && row_out[r]) ? o : kOob;
         roff[r] = RHS ? voff[r] / (uint32_t)(sizeof(Real) / sizeof(float)) : 0u;
     }
-    const int64_t plane_bytes = py * (int64_t)sizeof(Real);
-    const uint32_t plane_b32 = (uint32_t)plane_bytes;
+    const int64_t plane_bytes = py * (int64_t)sizeof(Real);  // < 0 with KREV
+    const uint32_t plane_b32 = (uint32_t)(plane_bytes < 0 ? -plane_bytes : plane_bytes);
     const char* src_b = reinterpret_cast<const char*>(src);
     const char* rhs_b = reinterpret_cast<const char*>(g.rhs);
     char* dst_b = reinterpret_cast<char*>(dst);
@@ -307,13 +318,18 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
             if (bnd) {
                 e = C[s][r];
             } else {
-                Real sum = P[s][r] + xo;
+                Real sum = KREV ? (P[s][r] + xo) + D[KREV ? s : 0][r] : P[s][r] + xo;
                 if (RHS) sum = sum + (Real)rr[RHS ? 2 * s : 0][r];
                 e = sum * c6;
                 if (WT) e = C[s][r] + omega * (e - C[s][r]);
                 if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
             }
-            P[s][r] = inpl + C[s][r];
+            if (KREV) {
+                P[s][r] = inpl;
+                D[KREV ? s : 0][r] = C[s][r];
+            } else {
+                P[s][r] = inpl + C[s][r];
+            }
             C[s][r] = xo;
             return e;
         };
@@ -350,32 +366,40 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     // Compressed grid: before a chunk of U steps, publish this tile's
     // progress and wait until the dependees have consumed every storage plane
     // the chunk's stores overwrite.  Done once per chunk, so that the steps
-    // themselves stay straight-line code.
+    // themselves stay straight-line code.  The dependees' words are read one
+    // chunk ahead, and only while what the tile knows does not already cover
+    // the next chunk's stores (each read goes past the L2 to memory shared by
+    // all XCDs).  Publishing less often measured slower: dependents wait.
+    auto need_of = [&](const int n0) {
+        // Stores of the chunk from n0 (and the one after its last step):
+        // planes up to a+n0+U-2T of the output, i.e. this storage plane in
+        // input-frame terms (planes outside the box are shift room nobody
+        // reads).  <= 0: nothing to wait for.
+        const int pe_hi = min(a + n0 + U - 2 * T, k1 - 1);
+        if (pe_hi < k0) return 0;
+        return min(p.dir > 0 || KREV ? pe_hi - p.zshift : pe_hi + p.zshift, g.nz + 1) + 1;
+    };
     auto sync_chunk = [&](const int n0) {
         if (n0 > 0 && threadIdx.x == 0) {
             // all waves passed the barrier of step n0-1: planes up to
             // a+n0-2 are consumed
             flag_store(p.flags + (int64_t)tile * kFlagStride, a + n0 - 1);
         }
-        // Stores of this chunk (and the one after its last step): planes
-        // up to a+n0+U-2T of the output.
-        const int pe_hi = min(a + n0 + U - 2 * T, k1 - 1);
-        if (pe_hi >= k0) {
-            // Storage plane overwritten, in input-frame terms; planes outside
-            // the box are shift room nobody reads.
-            const int ow = min(p.dir > 0 ? pe_hi - T : pe_hi + T, g.nz + 1);
-            const int need = ow + 1;
-            if (need > 0 && known < need) {
-                int v0 = fl_ahead;
+        const int need = need_of(n0);
+        if (need > 0 && known < need) {
+            int v0 = fl_ahead;
 #pragma unroll
-                for (int o = 1; o < 8; o <<= 1) v0 = min(v0, __shfl_xor(v0, o, 64));
-                known = max(known, __builtin_amdgcn_readfirstlane(v0));
-            }
-            if (__builtin_expect(need > 0 && known < need, 0))
-                known = wait_progress(p.flags, dep, need, p.spin_limit, p.err);
+            for (int o = 1; o < 8; o <<= 1) v0 = min(v0, __shfl_xor(v0, o, 64));
+            known = max(known, __builtin_amdgcn_readfirstlane(v0));
         }
-        // Read one chunk ahead, before the chunk's plane loads.
-        fl_ahead = dep >= 0 ? flag_load(p.flags + (int64_t)dep * kFlagStride) : kDone;
+        if (__builtin_expect(need > 0 && known < need, 0))
+            known = wait_progress(p.flags, dep, need, p.spin_limit, p.err);
+        // Read ahead, before the chunk's plane loads.  A skipped read leaves
+        // `known` (never more than the dependees' true progress).
+        if (known < need_of(n0 + U))
+            fl_ahead = dep >= 0 ? flag_load(p.flags + (int64_t)dep * kFlagStride) : kDone;
+        else
+            fl_ahead = dep >= 0 ? known : kDone;
         // The chunk's stores must follow the reads of the progress words.
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     };
@@ -481,7 +505,8 @@ __device__ __forceinline__ void finish_team(const TripParams& p, int tile, int t
 //         items (team, tile) from one ticket counter in team-major order,
 //         so every item an item waits for has a smaller ticket (no
 //         deadlock, whatever number of workgroups is resident).
-template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false>
+template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false,
+          bool KREV = false>
 __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 {
     constexpr bool FLAGS = MODE == 1;
@@ -499,7 +524,10 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             tile = xcd_tile(blockIdx.x, p.ntiles);
         } else {
             __syncthreads();  // previous tile finished with tile_sh and xch
-            if (threadIdx.x == 0) tile_sh = atomicAdd(p.ticket, 1);
+            if (threadIdx.x == 0)
+                tile_sh = MODE == 1 && p.groups > 1
+                              ? claim_grouped(p.gcnt, blockIdx.x & 7, p.chunk, p.ntiles)
+                              : atomicAdd(p.ticket, 1);
             __syncthreads();
             // Uniform across the workgroup: read it into a scalar register,
             // so that the per-plane buffer descriptors built from it stay
@@ -512,7 +540,13 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
                 tile = t - team * p.ntiles;
             } else {
                 if (t >= p.ntiles) return;
-                tile = (MODE == 1 && p.dir < 0) ? p.ntiles - 1 - t : t;
+                tile = t;
+                if (MODE == 1 && p.dir < 0) {
+                    // mirrored order: all axes, or i and j only in the
+                    // k-mirrored view (whose k already runs backwards)
+                    const int pl = p.tiles_x * p.tiles_y;
+                    tile = KREV ? (t / pl) * pl + (pl - 1 - t % pl) : p.ntiles - 1 - t;
+                }
             }
         }
         Geo g;
@@ -567,15 +601,16 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             wait_team(p.flags, p.done, p.err, p.tiles_x, p.tiles_y, p.segs, p.ntiles,
                       p.looseness, p.spin_limit, tile, team);
         if (interior_tile)
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, false, WT>(p, g, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, false, WT, KREV>(p, g, tile, xch);
         else
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, true, WT>(p, g, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, true, WT, KREV>(p, g, tile, xch);
         if (MODE == 3) finish_team(p, tile, team);
     }
 }
 
 // Launches one trip in MODE with tile shape (T, R, W).
-template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false>
+template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false,
+          bool KREV = false>
 hipError_t launch_mode(const TripParams& p, hipStream_t s)
 {
     const dim3 block(64 * W);
@@ -591,24 +626,34 @@ hipError_t launch_mode(const TripParams& p, hipStream_t s)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&trip_kernel<Real, T, R, W, PF, RHS, MODE, WT>),
+            &per_cu,
+            reinterpret_cast<const void*>(&trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, KREV>),
             64 * W, 0);
     if (e != hipSuccess) return e;
     int grid = cus * (per_cu > 0 ? per_cu : 1);
     const int64_t items = MODE == 3 ? (int64_t)p.ntiles * p.teams : p.ntiles;
     if (grid > items) grid = (int)items;
-    hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE, WT>), dim3(grid), block,
-                       0, s, p);
+    TripParams q = p;
+    // Per-XCD claim groups need a workgroup in every group; a chunk is the
+    // tiles one XCD holds at a time.
+    if (MODE == 1 && q.groups > 1) {
+        if (grid >= kClaimGroups)
+            q.chunk = grid / kClaimGroups;
+        else
+            q.groups = 1;
+    }
+    hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, KREV>), dim3(grid), block,
+                       0, s, q);
     return hipGetLastError();
 }
 
 // Launches the compiled tile shape `c` of one precision, rhs flag and mode.
-template <typename Real, bool RHS, int MODE, bool WT = false>
+template <typename Real, bool RHS, int MODE, bool WT = false, bool KREV = false>
 hipError_t dispatch_unit(const TripConfig& c, const TripParams& p, hipStream_t s)
 {
 #define JACOBI_CASE(T_, R_, W_)                     \
     if (c.T == T_ && c.R == R_ && c.W == W_)        \
-        return launch_mode<Real, T_, R_, W_, kPrefetch, RHS, MODE, WT>(p, s);
+        return launch_mode<Real, T_, R_, W_, kPrefetch, RHS, MODE, WT, KREV>(p, s);
     JACOBI_TRIP_CFGS(JACOBI_CASE)
 #undef JACOBI_CASE
     return hipErrorInvalidValue;

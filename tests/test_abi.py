@@ -126,7 +126,12 @@ def test_sizes():
     d.layout = 1
     d.t = 3
     assert lib.jacobi_grid_bytes(ctypes.byref(d), ctypes.byref(n)) == 0
-    assert n.value == 18 * 14 * 12 * 8   # box plus 2t shift planes per axis
+    # box plus 2t shift planes in i and j, 2t + 2E in k with E = 2t
+    assert n.value == 18 * 14 * (6 + 6 + 12) * 8
+    d.seg_len = 8  # caps E at seg_len - 2t = 2
+    assert lib.jacobi_grid_bytes(ctypes.byref(d), ctypes.byref(n)) == 0
+    assert n.value == 18 * 14 * (6 + 6 + 4) * 8
+    d.seg_len = 0
     d.dtype = 1
     assert lib.jacobi_workspace_size(ctypes.byref(d), ctypes.byref(n)) == 0
     assert n.value >= 3 * 12 * 8 * 6 * 4

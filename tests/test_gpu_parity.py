@@ -65,6 +65,51 @@ def test_compressed_trips_bitwise(t, dims):
     _assert_same(got, want, "compressed t=%d %s" % (t, dims))
 
 
+@pytest.mark.parametrize("t,dims,seg_len", [
+    (5, (70, 45, 37), 0),       # E = 2t, one k segment
+    (5, (130, 67, 90), 30),     # E = 2t, three segments of 30 planes
+    (4, (70, 45, 60), 11),      # E capped at seg_len - 2t = 3
+    (3, (41, 70, 52), 0),
+    (6, (70, 45, 37), 0),       # t > 5: backward trips stream upwards, E = 0
+])
+def test_compressed_uneven_calls_bitwise(t, dims, seg_len):
+    """Compressed trips over sweep counts that are not multiples of t, in
+    uneven calls: remainder trips, trips the planner shortens to keep both
+    shift offsets in range, backward trips in the k-mirrored view and the
+    extra shift along k (planes of shift room per the layout)."""
+    from paper_1006_3148_amd import Jacobi
+    nx, ny, nz = dims
+    box = synth.uniform_box(nx, ny, nz, seed=400 + t)
+    calls = [1, 7, 3, 2 * t, 5, 1, 4 * t + 3]
+    print("case compressed uneven t=%d dims=%s seg_len=%d calls=%s"
+          % (t, dims, seg_len, calls), flush=True)
+    j = Jacobi(box, t=t, layout="compressed", seg_len=seg_len)
+    done = 0
+    for c in calls:
+        j.sweep(c)
+        done += c
+        _assert_same(j.box(), oracle.sweeps_f64(box, done),
+                     "compressed uneven t=%d %s after %d" % (t, dims, done))
+    j.close()
+
+
+@pytest.mark.parametrize("env", [{"JACOBI_KREV": "0"}, {"JACOBI_XCD_ORDER": "0"},
+                                 {"JACOBI_ZEXTRA": "0"}])
+def test_compressed_variants_same_bits(env, monkeypatch):
+    """Backward trips streaming upwards (no extra k shift), one ticket counter
+    instead of the per-XCD claim groups, and no extra k shift all give the
+    default path's bits."""
+    box = synth.uniform_box(130, 67, 60, seed=431)
+    n = 23
+    print("case compressed variant %s" % env, flush=True)
+    want, _ = _run(box, n, t=5, layout="compressed")
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    got, _ = _run(box, n, t=5, layout="compressed")
+    _assert_same(got, want, "compressed variant %s" % env)
+    _assert_same(got, oracle.sweeps_f64(box, n), "compressed variant %s vs oracle" % env)
+
+
 def _compiled_shapes():
     from paper_1006_3148_amd.solver import tile_supported
     out = []
