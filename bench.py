@@ -469,7 +469,7 @@ def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024, budget=0.0, layout=
     """Sweeps and seconds to ||r|| <= 1e-8 ||r0|| from the zero start with
     sine-mode faces (seed 3): FP64 blocked (t), FP32-refined (FP32 sweeps of
     the correction equation, FP64 residual and update) and plain FP64 single
-    sweeps (t=1).
+    sweeps (t=1, A/B grids whatever `layout` the blocked forms use).
 
     Each solve runs in calls of 16 checks with r0 fixed, printing progress.
     With budget > 0 (seconds) a form stops when its budget is spent; the rest
@@ -495,7 +495,8 @@ def bench_time_to_tol(torch, n, t, rel_tol=1e-8, check=1024, budget=0.0, layout=
     for name, kw in (("f64_blocked", dict(t=t)),
                      ("f32_refined", dict(t=t, dtype="f32_refined", inner_sweeps=check)),
                      ("f64_single_sweep", dict(t=1))):
-        j = Jacobi(box, layout=layout, **kw)
+        # plain Jacobi (the single-sweep baseline) keeps separate A/B grids
+        j = Jacobi(box, layout="ab" if name == "f64_single_sweep" else layout, **kw)
         if r0 is None:
             r0, _ = j.residual()
             res["r0"] = r0
