@@ -90,8 +90,9 @@ __device__ __forceinline__ void load_voxel(const void* __restrict__ xin, int d, 
 
 // EPI 0: y = bf16(relu(acc + bias)); 1: y = acc + bias (FP32);
 // 2: dx = (accum ? dx : 0) + acc, zeroed where mask <= 0 (FP32).
+// Three waves per SIMD (three workgroups of 41 KB LDS per CU).
 template <bool IN_F32, int EPI, bool FLIP>
-__global__ __launch_bounds__(256) void conv3_s1_kernel(
+__global__ __launch_bounds__(256, 3) void conv3_s1_kernel(
     const void* __restrict__ xin, int d, const uint16_t* __restrict__ w,
     const float* __restrict__ bias, void* __restrict__ yout, int accum,
     const uint16_t* __restrict__ mask, int zseg)
@@ -164,17 +165,37 @@ __global__ __launch_bounds__(256) void conv3_s1_kernel(
         const bool more = z + 2 <= z1;  // plane z+2 feeds output plane z+1
         Voxel<IN_F32> nxt[2];
         if (more) stage_load(z + 2, nxt);
+        // The four output rows of this wave at once: every input fragment
+        // (x row 4*wave + yo of plane z+dz, shift dx) is read from LDS once
+        // and feeds the taps of up to three output rows.  Each row still sums
+        // its taps in ascending order.
+        v4f acc4[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc4[r] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+            for (int yo = -1; yo <= 4; ++yo) {
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const v4s bv = __builtin_bit_cast(
+                        v4s,
+                        lds[(z + dz + 4) & 3][(kq * kH + 4 * wave + yo + 1) * kH + m + 1 + dx]);
+#pragma unroll
+                    for (int dy = 1; dy >= -1; --dy) {
+                        const int r = yo - dy;
+                        if (r < 0 || r > 3) continue;
+                        const int t = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                        acc4[r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], bv, acc4[r],
+                                                                             0, 0, 0);
+                    }
+                }
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int yr = 4 * wave + r;
-            v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int t = 0; t < 27; ++t) {
-                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                const v4s bv = __builtin_bit_cast(
-                    v4s, lds[(z + dz + 4) & 3][(kq * kH + yr + 1 + dy) * kH + m + 1 + dx]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[t], bv, acc, 0, 0, 0);
-            }
+            const v4f acc = acc4[r];
             const int gx = x0 + m, gy = y0 + yr;
             if (gx < d && gy < d) {
                 const int64_t base = ((((int64_t)z * d + gy) * d + gx) << 4) + 4 * kq;
@@ -219,7 +240,14 @@ hipError_t launch_s1(const void* x, int d, const uint16_t* w, const float* b, vo
                      bool accum, const uint16_t* mask, hipStream_t s)
 {
     const int tiles = ((d + kT - 1) / kT) * ((d + kT - 1) / kT);
-    int zsegs = (1024 + tiles - 1) / tiles;
+    // As many z runs as fill the resident workgroups (three per CU) in one
+    // round: a launch of 1.33 rounds leaves two thirds of its second round
+    // idle.
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    int zsegs = 3 * cus / tiles;
     const int max_segs = (d + 3) / 4;  // runs of at least 4 planes
     if (zsegs > max_segs) zsegs = max_segs;
     if (zsegs < 1) zsegs = 1;
@@ -238,13 +266,14 @@ hipError_t launch_s1(const void* x, int d, const uint16_t* w, const float* b, vo
 // the plane of x shifted by the tap.  Both planes are held in LDS channel-
 // major ([c][y][x]), so a lane's four consecutive voxels are one 8-byte
 // word; an x shift of one voxel is assembled from two aligned dwords with
-// v_alignbit.  Waves split the taps (t = wave, wave+4, ...), every wave
-// sweeps all rows.
+// v_alignbit.  Each wave owns four rows of the tile and all 27 taps (27
+// accumulators): one x row, read once with its three shifts, feeds the taps
+// of up to three dy rows, so LDS delivers about half an operand fragment per
+// MFMA instead of two.  The four waves' sums meet in LDS in a fixed order.
 constexpr int kDyStride = kT * kT + 8;    // bf16 per channel, padded (banks)
 constexpr int kXRow = kT + 8;             // x = -4 .. kT+3 at element x + 4
 constexpr int kXPlane = kH * kXRow;       // rows y = -1 .. kT
 constexpr int kXStride = kXPlane + 8;     // bf16 per channel, padded
-constexpr int kTapsPerWave = 7;
 
 __device__ __forceinline__ v4s words_to_v4s(uint32_t lo, uint32_t hi)
 {
@@ -275,9 +304,9 @@ __global__ __launch_bounds__(256) void conv3_s1_wgrad_kernel(
     for (int q = threadIdx.x; q < kSlots * 16 * kXStride; q += 256)
         (&xs[0][0])[q] = 0;
 
-    v4f acc[kTapsPerWave];
+    v4f acc[27];
 #pragma unroll
-    for (int u = 0; u < kTapsPerWave; ++u) acc[u] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < 27; ++u) acc[u] = (v4f){0.f, 0.f, 0.f, 0.f};
     float dbs[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) dbs[c] = 0.f;
@@ -353,34 +382,39 @@ __global__ __launch_bounds__(256) void conv3_s1_wgrad_kernel(
             load_dy(z + 1);
         }
         const uint16_t* yb = ys[z & 1];
-#pragma unroll 2
-        for (int yr = 0; yr < kT; ++yr) {
-            const uint2 aw =
-                *reinterpret_cast<const uint2*>(yb + m * kDyStride + yr * kT + 4 * kq);
-            const v4s a = words_to_v4s(aw.x, aw.y);
+        // dy rows 4*wave + r of this plane
+        v4s A[4];
 #pragma unroll
-            for (int u = 0; u < kTapsPerWave; ++u) {
-                const int t = wave + 4 * u;
-                if (t < 27) {
-                    const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                    const uint16_t* row = xs[(z + dz + 4) & 3] + m * kXStride +
-                                          (yr + 1 + dyy) * kXRow + 4 * kq + 4;
-                    v4s b;
-                    if (dx == 0) {
-                        const uint2 w2 = *reinterpret_cast<const uint2*>(row);
-                        b = words_to_v4s(w2.x, w2.y);
-                    } else if (dx < 0) {
-                        const uint32_t d0 = *reinterpret_cast<const uint32_t*>(row - 2);
-                        const uint2 w2 = *reinterpret_cast<const uint2*>(row);
-                        b = words_to_v4s(__builtin_amdgcn_alignbit(w2.x, d0, 16),
-                                         __builtin_amdgcn_alignbit(w2.y, w2.x, 16));
-                    } else {
-                        const uint2 w2 = *reinterpret_cast<const uint2*>(row);
-                        const uint32_t d3 = *reinterpret_cast<const uint32_t*>(row + 4);
-                        b = words_to_v4s(__builtin_amdgcn_alignbit(w2.y, w2.x, 16),
-                                         __builtin_amdgcn_alignbit(d3, w2.y, 16));
-                    }
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[u], 0, 0, 0);
+        for (int r = 0; r < 4; ++r) {
+            const uint2 aw = *reinterpret_cast<const uint2*>(yb + m * kDyStride +
+                                                             (4 * wave + r) * kT + 4 * kq);
+            A[r] = words_to_v4s(aw.x, aw.y);
+        }
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+            const uint16_t* plane = xs[(z + dz + 4) & 3] + m * kXStride + 4 * kq + 4;
+#pragma unroll
+            for (int yo = -1; yo <= 4; ++yo) {
+                // x row 4*wave + yo at shifts dx = -1, 0, +1
+                const uint16_t* row = plane + (4 * wave + yo + 1) * kXRow;
+                const uint32_t d0 = *reinterpret_cast<const uint32_t*>(row - 2);
+                const uint2 w2 = *reinterpret_cast<const uint2*>(row);
+                const uint32_t d3 = *reinterpret_cast<const uint32_t*>(row + 4);
+                const v4s bm = words_to_v4s(__builtin_amdgcn_alignbit(w2.x, d0, 16),
+                                            __builtin_amdgcn_alignbit(w2.y, w2.x, 16));
+                const v4s b0 = words_to_v4s(w2.x, w2.y);
+                const v4s bp = words_to_v4s(__builtin_amdgcn_alignbit(w2.y, w2.x, 16),
+                                            __builtin_amdgcn_alignbit(d3, w2.y, 16));
+#pragma unroll
+                for (int dyy = -1; dyy <= 1; ++dyy) {
+                    const int r = yo - dyy;  // dy row 4*wave + r meets x row 4*wave + r + dyy
+                    if (r < 0 || r > 3) continue;
+                    const int tb = (dz + 1) * 9 + (dyy + 1) * 3;
+                    acc[tb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[r], bm, acc[tb], 0, 0, 0);
+                    acc[tb + 1] =
+                        __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[r], b0, acc[tb + 1], 0, 0, 0);
+                    acc[tb + 2] =
+                        __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[r], bp, acc[tb + 2], 0, 0, 0);
                 }
             }
         }
@@ -391,16 +425,32 @@ __global__ __launch_bounds__(256) void conv3_s1_wgrad_kernel(
         __syncthreads();
     }
 
-    // partials: D[m = co = 4kq + j][n = ci = m] of tap t
-    float* out = part + (int64_t)blk * kConvP;
+    // Partials D[m = co = 4kq + j][n = ci = m] of tap u, summed over the
+    // waves as (w0 + w2) + (w1 + w3) through two LDS copies (the x planes are
+    // no longer needed: the plane loop ended with a barrier).
+    constexpr int kTapW = 27 * 256;
+    float* sum2 = reinterpret_cast<float*>(&xs[0][0]);
+    static_assert(2 * kTapW * sizeof(float) <= sizeof(uint16_t) * kSlots * 16 * kXStride,
+                  "the wave sums must fit in the x planes");
+    if (wave < 2) {
 #pragma unroll
-    for (int u = 0; u < kTapsPerWave; ++u) {
-        const int t = wave + 4 * u;
-        if (t < 27) {
+        for (int u = 0; u < 27; ++u)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) out[t * 256 + (4 * kq + j) * 16 + m] = acc[u][j];
-        }
+            for (int j = 0; j < 4; ++j)
+                sum2[wave * kTapW + u * 256 + (4 * kq + j) * 16 + m] = acc[u][j];
     }
+    __syncthreads();
+    if (wave >= 2) {
+#pragma unroll
+        for (int u = 0; u < 27; ++u)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                sum2[(wave - 2) * kTapW + u * 256 + (4 * kq + j) * 16 + m] += acc[u][j];
+    }
+    __syncthreads();
+    float* out = part + (int64_t)blk * kConvP;
+    for (int q = threadIdx.x; q < kTapW; q += 256) out[q] = sum2[q] + sum2[kTapW + q];
+    __syncthreads();  // the bias tree below reuses the same LDS
     // bias gradient: fixed-order tree over the 256 threads
 #pragma unroll
     for (int c = 0; c < 16; ++c) red[threadIdx.x][c] = dbs[c];

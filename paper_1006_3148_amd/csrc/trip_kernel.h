@@ -497,8 +497,9 @@ __device__ __forceinline__ void finish_team(const TripParams& p, int tile, int t
 
 // MODE 0: one problem, tile = f(blockIdx) (A/B; kernel boundary between
 //         trips is the only synchronization).
-// MODE 1: one problem, tiles from a ticket counter, progress flags
-//         (compressed single grid).
+// MODE 1: one problem, tiles from a ticket counter or per-XCD claim groups,
+//         progress flags (compressed single grid); KREV: a backward trip in
+//         the k-mirrored view.
 // MODE 2: a batch of independent problems described by p.table; tiles of all
 //         problems from one ticket counter; A/B parity read from *p.parity.
 // MODE 3: one problem, p.teams trips in one persistent launch (A/B): work
