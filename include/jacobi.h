@@ -145,7 +145,8 @@ int jacobi_workspace_size(const jacobi_desc *d, size_t *bytes);
  *   JACOBI_SPIN_LIMIT=n   bound on a compressed tile's waits (then
  *                         JACOBI_ETIMEOUT);
  *   JACOBI_XCD_ORDER=0    compressed trips take tiles from one ticket counter
- *                         instead of per-XCD claim groups;
+ *                         instead of per-XCD claim groups (used for trips of
+ *                         4 or more sweeps);
  *   JACOBI_KREV=0         backward compressed trips stream k upwards (E = 0);
  *   JACOBI_ZEXTRA=planes  the extra k shift E of compressed trips. */
 int jacobi_create(const jacobi_desc *d, jacobi_t **out);

@@ -373,7 +373,9 @@ hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
     p.dir = dir;
     p.flags = h->flags;
     p.ticket = h->ticket;
-    p.groups = h->xcd_order ? kClaimGroups : 1;
+    // Claim groups start a tile's dependees at about the same time as the
+    // tile rather than before it; that needs the slack of T >= 4 (5T steps).
+    p.groups = h->xcd_order && T >= 4 ? kClaimGroups : 1;
     p.gcnt = h->gcnt;
     p.zshift = zshift > 0 ? zshift : T;
     p.krev = krev ? 1 : 0;

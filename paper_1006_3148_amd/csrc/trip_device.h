@@ -84,11 +84,19 @@ constexpr int kDone = 0x7fffffff;
 // with one atomic add.  Every tile waits only for tiles earlier in O; a group
 // hands out its tiles in O order, so the earliest unfinished tile is claimed
 // as soon as a workgroup of its group is free, and its dependees are done:
-// the launch completes once every group has a workgroup resident.  Returns
-// the tile in O numbering, or ntiles when the group is exhausted.
+// the launch completes once every group has a workgroup resident.  When
+// every tile is resident at once (chunk = 0; one workgroup per tile), group
+// x is instead the x-th of eight near-equal ranges, sized like the
+// workgroups on XCD x: chunks of grid/8 would leave the remainder tiles to
+// one group, whose trip then takes two tile times.  Returns the tile in O
+// numbering, or ntiles when the group is exhausted.
 __device__ __forceinline__ int claim_grouped(int* gcnt, int xcd, int chunk, int ntiles)
 {
     const int k = atomicAdd(gcnt + xcd * kFlagStride, 1);
+    if (chunk == 0) {
+        const int q = ntiles >> 3, r = ntiles & 7;
+        return k < q + (xcd < r ? 1 : 0) ? xcd * q + min(xcd, r) + k : ntiles;
+    }
     const int64_t v = ((int64_t)(k / chunk) * kClaimGroups + xcd) * chunk + k % chunk;
     return v < ntiles ? (int)v : ntiles;
 }

@@ -636,12 +636,12 @@ hipError_t launch_mode(const TripParams& p, hipStream_t s)
     if (grid > items) grid = (int)items;
     TripParams q = p;
     // Per-XCD claim groups need a workgroup in every group; a chunk is the
-    // tiles one XCD holds at a time.
+    // tiles one XCD holds at a time (0: one workgroup per tile).
     if (MODE == 1 && q.groups > 1) {
-        if (grid >= kClaimGroups)
-            q.chunk = grid / kClaimGroups;
-        else
+        if (grid < kClaimGroups)
             q.groups = 1;
+        else
+            q.chunk = grid >= items ? 0 : grid / kClaimGroups;
     }
     hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, KREV>), dim3(grid), block,
                        0, s, q);
