@@ -212,6 +212,60 @@ __global__ __launch_bounds__(256) void conv_bwd_data_kernel(
     }
 }
 
+// Stride 2: dx[v] receives tap t only where v - d_t is even in every axis,
+// i.e. 1, 2, 4 or 8 taps by the parity class of v.  A wave takes 16 voxels of
+// one class along x (x = 2j + px, j = j0..j0+15, fixed y and z), so it runs
+// only its class's taps (27/8 on average instead of 27; the others added
+// exact zeros) and its dy sources are 16 consecutive voxels.
+__global__ __launch_bounds__(256) void conv_bwd_data_s2_kernel(
+    const float* __restrict__ dy, int dout, const uint16_t* __restrict__ wt,
+    float* __restrict__ dx, int din, int accum, const uint16_t* __restrict__ mask)
+{
+    const int lane = threadIdx.x & 63;
+    const int wid = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
+    const int half = (din + 1) >> 1;   // j values per parity
+    const int jt = (half + 15) >> 4;   // 16-voxel runs per (row, parity)
+    const int64_t nw = (int64_t)din * din * 2 * jt;
+    if (wid >= nw) return;
+    const int j0 = (wid % jt) * 16;
+    const int px = (wid / jt) & 1;
+    const int vy = (wid / (2 * jt)) % din;
+    const int vz = (int)(wid / (2 * (int64_t)jt * din));
+    const int m = lane & 15, kq = lane >> 4;
+    const int vx = 2 * (j0 + m) + px;  // this lane's voxel (A row m)
+    const int pz = vz & 1, py = vy & 1;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    // taps in ascending order: d in {0} for an even coordinate, {-1, +1} for an odd one
+    for (int dz = pz ? -1 : 0; dz <= (pz ? 1 : 0); dz += 2) {
+        const int oz = (vz - dz) >> 1;
+        if ((unsigned)oz >= (unsigned)dout) continue;
+        for (int dyy = py ? -1 : 0; dyy <= (py ? 1 : 0); dyy += 2) {
+            const int oy = (vy - dyy) >> 1;
+            if ((unsigned)oy >= (unsigned)dout) continue;
+            for (int dx_ = px ? -1 : 0; dx_ <= (px ? 1 : 0); dx_ += 2) {
+                const int t = (dz + 1) * 9 + (dyy + 1) * 3 + dx_ + 1;
+                const int ox = (vx - dx_) >> 1;
+                const bool ok = vx < din && (unsigned)ox < (unsigned)dout;
+                v4s a = {0, 0, 0, 0};
+                if (ok) a = f4_to_bf(dy + (((int64_t)oz * dout + oy) * dout + ox) * 16 + 4 * kq);
+                const v4s bw = load4bf(wt + ((int64_t)t * 16 + m) * 16 + 4 * kq);
+                acc = mfma16(a, bw, acc);
+            }
+        }
+    }
+    const int n = lane & 15;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int x = 2 * (j0 + 4 * kq + r) + px;
+        if (x >= din) continue;
+        const int64_t idx = (((int64_t)vz * din + vy) * din + x) * 16 + n;
+        float v = acc[r];
+        if (accum) v += dx[idx];
+        if (mask && !(bf2f(mask[idx]) > 0.f)) v = 0.f;
+        dx[idx] = v;
+    }
+}
+
 // -------------------------------------------------- conv weight grad ----
 // Per block: partial dw[t][co][ci] = sum over its output voxels o of
 // dy[o][co] * x[S*o + d_t][ci], and partial db[co] = sum dy[o][co].
@@ -641,6 +695,12 @@ hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* w, const uin
                          hipStream_t s)
 {
     if (stride == 1) return conv_bwd_data_s1(dy, din, w, dx, accum, mask, s);
+    if (stride == 2) {
+        const int64_t waves = (int64_t)din * din * 2 * ((((din + 1) >> 1) + 15) >> 4);
+        hipLaunchKernelGGL(conv_bwd_data_s2_kernel, dim3(blocks_for(waves, 4)), dim3(256), 0, s,
+                           dy, dout, wt, dx, din, accum ? 1 : 0, mask);
+        return hipGetLastError();
+    }
     const int64_t tiles = (int64_t)din * din * ((din + 15) / 16);
     const dim3 grid(blocks_for(tiles, 4));
     if (stride == 1)
