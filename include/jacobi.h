@@ -147,6 +147,8 @@ int jacobi_workspace_size(const jacobi_desc *d, size_t *bytes);
  *   JACOBI_XCD_ORDER=0    compressed trips take tiles from one ticket counter
  *                         instead of per-XCD claim groups (used for trips of
  *                         4 or more sweeps);
+ *   JACOBI_AB_BANDS=0     A/B trips of several workgroup generations give each
+ *                         XCD one contiguous range of tiles instead of bands;
  *   JACOBI_KREV=0         backward compressed trips stream k upwards (E = 0);
  *   JACOBI_ZEXTRA=planes  the extra k shift E of compressed trips. */
 int jacobi_create(const jacobi_desc *d, jacobi_t **out);

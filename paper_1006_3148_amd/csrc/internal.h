@@ -55,7 +55,8 @@ struct TripParams {
     float omega;
     int groups;                 // mode 1: per-XCD claim groups (> 1) or one
                                 // ticket counter (1)
-    int chunk;                  // mode 1 groups: tiles per chunk (set at launch)
+    int chunk;                  // mode 1 groups: tiles per chunk (set at
+                                // launch); mode 0: > 0 selects band order
     int* gcnt;                  // mode 1 groups: kClaimGroups counters, stride
                                 // kFlagStride ints (zeroed)
     int zshift;                 // mode 1: k shift of dst against src

@@ -150,6 +150,10 @@ struct jacobi_s {
     // falls back to one ticket counter
     bool xcd_order = true;
     bool krev = false;  // backward compressed trips use the k-mirrored view
+    // A/B trips of several generations of workgroups take tiles in band
+    // order (each generation one band of 256 consecutive tiles, 32 per XCD);
+    // JACOBI_AB_BANDS=0 gives every XCD one contiguous range instead
+    bool ab_bands = true;
     int* done = nullptr;     // per-team finished-tile counts (teams >= 2)
     float* e[2] = {nullptr, nullptr};
     float* rhs = nullptr;
@@ -377,6 +381,7 @@ hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
     // tile rather than before it; that needs the slack of T >= 4 (5T steps).
     p.groups = h->xcd_order && T >= 4 ? kClaimGroups : 1;
     p.gcnt = h->gcnt;
+    if (mode == 0 && h->ab_bands && pl.ntiles > kCUs) p.chunk = 1;  // band order (band_tile)
     p.zshift = zshift > 0 ? zshift : T;
     p.krev = krev ? 1 : 0;
     p.err = h->err;
@@ -822,6 +827,7 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     h->flags = h->gcnt + kClaimGroups * kFlagStride;
     if (const char* s = std::getenv("JACOBI_XCD_ORDER")) h->xcd_order = std::atoi(s) != 0;
     h->krev = compressed_krev(t);
+    if (const char* s = std::getenv("JACOBI_AB_BANDS")) h->ab_bands = std::atoi(s) != 0;
     h->flag_ints = L.flag_ints;
     h->done = reinterpret_cast<int*>(h->ws + L.done_off);
     if (d->dtype != JACOBI_F64) {

@@ -62,6 +62,19 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles)
     return x * q + min(x, r) + idx;
 }
 
+// Band order of a multi-generation A/B launch: the first bands*256 workgroups
+// run generation g = idx / 32 of XCD x = b % 8 (idx = b / 8) on tiles
+// g*256 + x*32 + idx % 32, so each generation covers 256 consecutive tiles,
+// 32 per XCD; the tail (a partial generation) is split into eight contiguous
+// ranges like xcd_tile.
+__device__ __forceinline__ int band_tile(int b, int ntiles)
+{
+    const int full = (ntiles >> 8) << 8;
+    if (b >= full) return full + xcd_tile(b - full, ntiles - full);
+    const int x = b & 7, idx = b >> 3;
+    return ((idx >> 5) << 8) + (x << 5) + (idx & 31);
+}
+
 __device__ __forceinline__ int flag_load(const int* f)
 {
     return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -522,7 +522,7 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
         int team = 0;
         if (MODE == 0) {
             if (iter > 0) return;
-            tile = xcd_tile(blockIdx.x, p.ntiles);
+            tile = p.chunk > 0 ? band_tile(blockIdx.x, p.ntiles) : xcd_tile(blockIdx.x, p.ntiles);
         } else {
             __syncthreads();  // previous tile finished with tile_sh and xch
             if (threadIdx.x == 0)

@@ -34,6 +34,7 @@ def main(argv=None):
     ap.add_argument("--rows-per-wave", type=int, default=0)
     ap.add_argument("--teams", type=int, default=0)
     ap.add_argument("--looseness", type=int, default=-1)
+    ap.add_argument("--seg-len", type=int, default=0, help="k planes per segment (0 = auto)")
     a = ap.parse_args(argv)
     import torch
     import synth
@@ -43,7 +44,8 @@ def main(argv=None):
     for t in [int(v) for v in a.t.split(",")]:
         sweeps = a.sweeps if a.sweeps > 0 else 4 * t
         j = Jacobi(box, t=t, layout=a.layout, dtype=a.dtype, tile_rows=a.tile_rows,
-                   rows_per_wave=a.rows_per_wave, teams=a.teams, looseness=a.looseness)
+                   rows_per_wave=a.rows_per_wave, teams=a.teams, looseness=a.looseness,
+                   seg_len=a.seg_len)
         j.sweep(sweeps)
         j.sync()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
