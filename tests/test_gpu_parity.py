@@ -110,6 +110,22 @@ def test_compressed_variants_same_bits(env, monkeypatch):
     _assert_same(got, oracle.sweeps_f64(box, n), "compressed variant %s vs oracle" % env)
 
 
+@pytest.mark.parametrize("t,dims,seg_len", [(5, (300, 250, 60), 8), (4, (200, 130, 90), 4)])
+def test_ab_band_order_bitwise(t, dims, seg_len, monkeypatch):
+    """A/B trips with several generations of workgroups (more tiles than CUs)
+    take tiles in band order with a split tail: bitwise the oracle and the
+    one-range-per-XCD order."""
+    nx, ny, nz = dims
+    box = synth.uniform_box(nx, ny, nz, seed=500 + t)
+    n = 2 * t + 3
+    print("case ab band order t=%d dims=%s seg_len=%d" % (t, dims, seg_len), flush=True)
+    got, info = _run(box, n, t=t, layout="ab", seg_len=seg_len)
+    _assert_same(got, oracle.sweeps_f64(box, n), "ab band order t=%d %s" % (t, dims))
+    monkeypatch.setenv("JACOBI_AB_BANDS", "0")
+    ranges, _ = _run(box, n, t=t, layout="ab", seg_len=seg_len)
+    _assert_same(got, ranges, "ab band order vs ranges t=%d %s" % (t, dims))
+
+
 def _compiled_shapes():
     from paper_1006_3148_amd.solver import tile_supported
     out = []
