@@ -465,6 +465,175 @@ __global__ __launch_bounds__(256) void conv3_s1_wgrad_kernel(
     if (threadIdx.x < 16) out[kConvW + threadIdx.x] = red[0][threadIdx.x];
 }
 
+// --------------------------------------------- stride-2 weight gradient ----
+// dW[t][co][ci] = sum_o bf16(dy[o][co]) x[2o + d_t][ci] and db[co] = sum_o
+// dy[o][co] over a 16 x 4 x zseg block of output voxels o, as per-block
+// partials.  MFMA K runs over the 16 voxels of an output row.  An input row
+// is held in LDS split by x parity (per channel: even columns 2j at element
+// j - ox0, odd columns 2j+1 at element 24 + j - ox0, j = ox0-1 .. ox0+15), so
+// the taps dx = 0 and +1 read aligned words and dx = -1 shifts the odd half by
+// one element with v_alignbit.  Each wave owns one output row and all 27 taps.
+constexpr int kS2Rows = 4;                   // output rows per block (one per wave)
+constexpr int kS2InRows = 2 * kS2Rows + 1;   // input rows 2*oy0-1 .. 2*oy0+7
+constexpr int kS2Row = 40;                   // elements per input row and channel
+constexpr int kS2Chan = kS2InRows * kS2Row + 8;  // per channel, padded
+constexpr int kS2DyChan = kS2Rows * kT + 8;
+
+__global__ __launch_bounds__(256) void conv3_s2_wgrad_kernel(
+    const uint16_t* __restrict__ x, int din, const float* __restrict__ dy, int dout, int zseg,
+    float* __restrict__ part)
+{
+    __shared__ __align__(16) uint16_t xs[4][16 * kS2Chan];
+    __shared__ __align__(16) uint16_t ys[16 * kS2DyChan];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int tiles_x = (dout + kT - 1) / kT;
+    const int ox0 = (blockIdx.x % tiles_x) * kT;
+    const int oy0 = (blockIdx.x / tiles_x) * kS2Rows;
+    const int z0 = blockIdx.y * zseg;
+    const int z1 = min(z0 + zseg, dout);
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+
+    // the pad elements are read (and discarded) by the shifted fragments
+    for (int q = threadIdx.x; q < 4 * 16 * kS2Chan; q += 256) (&xs[0][0])[q] = 0;
+
+    v4f acc[27];
+#pragma unroll
+    for (int u = 0; u < 27; ++u) acc[u] = (v4f){0.f, 0.f, 0.f, 0.f};
+    float dbs[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) dbs[c] = 0.f;
+
+    // one input plane iz into slot: 9 rows x 33 columns (2*ox0-1 .. 2*ox0+31)
+    auto stage_x = [&](int iz, int slot) {
+        constexpr int kCols = 2 * kT + 1;
+        for (int q = threadIdx.x; q < kS2InRows * kCols; q += 256) {
+            const int r = q / kCols, cx = q % kCols;
+            const int ix = 2 * ox0 - 1 + cx, iy = 2 * oy0 - 1 + r;
+            const bool in = (unsigned)ix < (unsigned)din && (unsigned)iy < (unsigned)din &&
+                            (unsigned)iz < (unsigned)din;
+            const uint4* p = reinterpret_cast<const uint4*>(x) +
+                             (in ? (((int64_t)iz * din + iy) * din + ix) * 2 : 0);
+            const uint4 a = in ? p[0] : make_uint4(0, 0, 0, 0);
+            const uint4 b = in ? p[1] : make_uint4(0, 0, 0, 0);
+            const uint32_t wds[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+            // cx odd: even column 2j at j - ox0 = (cx - 1) / 2; cx even: odd
+            // column 2j + 1 at 24 + j - ox0 = 23 + cx / 2
+            const int e = r * kS2Row + ((cx & 1) ? (cx - 1) / 2 : 23 + cx / 2);
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                xs[slot][c * kS2Chan + e] =
+                    (uint16_t)((c & 1) ? (wds[c >> 1] >> 16) : (wds[c >> 1] & 0xffff));
+        }
+    };
+    // the dy rows of output plane oz (bias sums from the FP32 values)
+    auto stage_dy = [&](int oz) {
+        if (threadIdx.x < kS2Rows * kT) {
+            const int r = threadIdx.x / kT, cx = threadIdx.x % kT;
+            const int ox = ox0 + cx, oy = oy0 + r;
+            const bool in = ox < dout && oy < dout;
+            const float4* p = reinterpret_cast<const float4*>(dy) +
+                              (in ? (((int64_t)oz * dout + oy) * dout + ox) * 4 : 0);
+            float f[16];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float4 v = in ? p[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                f[4 * k] = v.x;
+                f[4 * k + 1] = v.y;
+                f[4 * k + 2] = v.z;
+                f[4 * k + 3] = v.w;
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                dbs[c] += f[c];
+                ys[c * kS2DyChan + r * kT + cx] = bf16_rne(f[c]);
+            }
+        }
+    };
+
+    __syncthreads();  // pad zeroing before the first stores
+    stage_x(2 * z0 - 1, (2 * z0 - 1 + 8) & 3);
+    for (int oz = z0; oz < z1; ++oz) {
+        stage_x(2 * oz, (2 * oz + 8) & 3);
+        stage_x(2 * oz + 1, (2 * oz + 1 + 8) & 3);
+        stage_dy(oz);
+        __syncthreads();
+        const uint2 aw =
+            *reinterpret_cast<const uint2*>(ys + m * kS2DyChan + wave * kT + 4 * kq);
+        const v4s A = words_to_v4s(aw.x, aw.y);
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+            const uint16_t* plane = xs[(2 * oz + dz + 8) & 3] + m * kS2Chan;
+#pragma unroll
+            for (int dyy = -1; dyy <= 1; ++dyy) {
+                const uint16_t* row = plane + (2 * wave + 1 + dyy) * kS2Row;
+                const uint2 ev = *reinterpret_cast<const uint2*>(row + 4 * kq);
+                const uint2 od = *reinterpret_cast<const uint2*>(row + 24 + 4 * kq);
+                const uint32_t d0 = *reinterpret_cast<const uint32_t*>(row + 22 + 4 * kq);
+                const v4s bm = words_to_v4s(__builtin_amdgcn_alignbit(od.x, d0, 16),
+                                            __builtin_amdgcn_alignbit(od.y, od.x, 16));
+                const v4s b0 = words_to_v4s(ev.x, ev.y);
+                const v4s bp = words_to_v4s(od.x, od.y);
+                const int tb = (dz + 1) * 9 + (dyy + 1) * 3;
+                acc[tb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, bm, acc[tb], 0, 0, 0);
+                acc[tb + 1] =
+                    __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, b0, acc[tb + 1], 0, 0, 0);
+                acc[tb + 2] =
+                    __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, bp, acc[tb + 2], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // the slots of planes 2oz-1 and 2oz are refilled next
+    }
+
+    // wave sums (w0 + w2) + (w1 + w3) through LDS, taps 0..13 then 14..26
+    // (the two copies of all 27 would not fit in the x slots), then the bias
+    // tree
+    constexpr int kHalfW = 14 * 256;
+    float* sum2 = reinterpret_cast<float*>(&xs[0][0]);
+    static_assert(2 * kHalfW * sizeof(float) <= sizeof(uint16_t) * 4 * 16 * kS2Chan,
+                  "the wave sums must fit in the x slots");
+    float* out = part + (int64_t)blk * kConvP;
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        const int u0 = 14 * hf, nu = hf ? 13 : 14;
+        if (wave < 2) {
+#pragma unroll
+            for (int u = 0; u < 27; ++u)
+                if (u / 14 == hf)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        sum2[wave * kHalfW + (u - u0) * 256 + (4 * kq + j) * 16 + m] = acc[u][j];
+        }
+        __syncthreads();
+        if (wave >= 2) {
+#pragma unroll
+            for (int u = 0; u < 27; ++u)
+                if (u / 14 == hf)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        sum2[(wave - 2) * kHalfW + (u - u0) * 256 + (4 * kq + j) * 16 + m] +=
+                            acc[u][j];
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < nu * 256; q += 256)
+            out[u0 * 256 + q] = sum2[q] + sum2[kHalfW + q];
+        __syncthreads();
+    }
+    float(*red)[17] = reinterpret_cast<float(*)[17]>(&xs[0][0]);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) red[threadIdx.x][c] = dbs[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) red[threadIdx.x][c] += red[threadIdx.x + w][c];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 16) out[kConvW + threadIdx.x] = red[0][threadIdx.x];
+}
+
 }  // namespace
 
 hipError_t conv_fwd_s1(const uint16_t* x, int d, const uint16_t* w, const float* b,
@@ -508,6 +677,39 @@ hipError_t conv_bwd_weight_s1(const uint16_t* x, const float* dy, int d, float* 
     const int tiles = ((d + kT - 1) / kT) * ((d + kT - 1) / kT);
     hipLaunchKernelGGL(conv3_s1_wgrad_kernel, dim3(tiles, blocks / tiles), dim3(256), 0, s, x,
                        dy, d, zseg, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_partials(part, blocks, grad_w_b, s);
+}
+
+}  // namespace nn
+}  // namespace jacobi_impl
+
+namespace jacobi_impl {
+namespace nn {
+
+// Blocks of the stride-2 weight-gradient launch for output edge dout (0 when
+// one plane's tiles alone exceed kMaxWgradBlocks).
+int wgrad_s2_blocks(int dout, int* zseg_out)
+{
+    const int tiles = ((dout + kT - 1) / kT) * ((dout + kS2Rows - 1) / kS2Rows);
+    if (tiles > kMaxWgradBlocks) return 0;
+    int zsegs = kMaxWgradBlocks / tiles;
+    if (zsegs > dout) zsegs = dout;
+    if (zsegs < 1) zsegs = 1;
+    const int zseg = (dout + zsegs - 1) / zsegs;
+    if (zseg_out) *zseg_out = zseg;
+    return tiles * ((dout + zseg - 1) / zseg);
+}
+
+hipError_t conv_bwd_weight_s2(const uint16_t* x, int din, const float* dy, int dout,
+                              float* part, float* grad_w_b, hipStream_t s)
+{
+    int zseg = 1;
+    const int blocks = wgrad_s2_blocks(dout, &zseg);
+    const int tiles = ((dout + kT - 1) / kT) * ((dout + kS2Rows - 1) / kS2Rows);
+    hipLaunchKernelGGL(conv3_s2_wgrad_kernel, dim3(tiles, blocks / tiles), dim3(256), 0, s, x,
+                       din, dy, dout, zseg, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return reduce_partials(part, blocks, grad_w_b, s);

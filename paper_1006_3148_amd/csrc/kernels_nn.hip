@@ -733,6 +733,8 @@ hipError_t conv_bwd_weight(const uint16_t* x, int din, const float* dy, int dout
 {
     if (stride == 1 && wgrad_s1_blocks(din, nullptr) > 0)
         return conv_bwd_weight_s1(x, dy, din, part, grad_w_b, s);
+    if (stride == 2 && wgrad_s2_blocks(dout, nullptr) > 0)
+        return conv_bwd_weight_s2(x, din, dy, dout, part, grad_w_b, s);
     const int blocks = wgrad_blocks(dout);
     const int64_t nchunk = ((int64_t)dout * dout * dout + 15) / 16;
     const int cpw = (int)((nchunk + (int64_t)blocks * 4 - 1) / ((int64_t)blocks * 4));

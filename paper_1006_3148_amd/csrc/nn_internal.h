@@ -33,6 +33,11 @@ hipError_t conv_bwd_data_s1(const float* dy, int d, const uint16_t* w, float* dx
 // Weight-gradient partials: at most kMaxWgradBlocks blocks of kConvP floats.
 constexpr int kMaxWgradBlocks = 512;
 int wgrad_s1_blocks(int d, int* zseg);
+// Stride-2 weight gradient (input edge din, output edge dout) through the
+// partial buffer (at most kMaxWgradBlocks blocks; 0 blocks = not usable).
+int wgrad_s2_blocks(int dout, int* zseg);
+hipError_t conv_bwd_weight_s2(const uint16_t* x, int din, const float* dy, int dout,
+                              float* part, float* grad_w_b, hipStream_t s);
 hipError_t conv_bwd_weight_s1(const uint16_t* x, const float* dy, int d, float* part,
                               float* grad_w_b, hipStream_t s);
 // grad[q] += sum over blocks b (fixed order) of part[b * kConvP + q].
