@@ -164,54 +164,8 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(
 // ---------------------------------------------------- conv data grad ----
 // dx[v] (+)= sum_t W_t^T dy[(v - d_t)/S] over the taps with an integral
 // in-range source; then dx *= (mask[v] > 0) if a mask (the ReLU output that
-// produced this conv's input) is given.  wt: [27][Cin][Cout].
-template <int S>
-__global__ __launch_bounds__(256) void conv_bwd_data_kernel(
-    const float* __restrict__ dy, int dout, const uint16_t* __restrict__ wt,
-    float* __restrict__ dx, int din, int accum, const uint16_t* __restrict__ mask)
-{
-    const int lane = threadIdx.x & 63;
-    const int wid = (blockIdx.x * (blockDim.x >> 6)) + (threadIdx.x >> 6);
-    const int xt = (din + 15) >> 4;
-    const int64_t ntile = (int64_t)din * din * xt;
-    if (wid >= ntile) return;
-    const int vx0 = (wid % xt) * 16;
-    const int vy = (wid / xt) % din;
-    const int vz = wid / (xt * din);
-    const int m = lane & 15, kq = lane >> 4;
-    const int vx = vx0 + m;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx_ = t % 3 - 1;
-        int oz = vz - dz, oy = vy - dyy, ox = vx - dx_;
-        bool ok = vx < din;
-        if (S == 2) {
-            ok = ok && !(oz & 1) && !(oy & 1) && !(ox & 1);
-            oz >>= 1;
-            oy >>= 1;
-            ox >>= 1;
-        }
-        ok = ok && (unsigned)oz < (unsigned)dout && (unsigned)oy < (unsigned)dout &&
-             (unsigned)ox < (unsigned)dout;
-        v4s a = {0, 0, 0, 0};
-        if (ok) a = f4_to_bf(dy + (((int64_t)oz * dout + oy) * dout + ox) * 16 + 4 * kq);
-        const v4s bw = load4bf(wt + ((int64_t)t * 16 + m) * 16 + 4 * kq);
-        acc = mfma16(a, bw, acc);
-    }
-    const int n = lane & 15;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int x = vx0 + 4 * kq + r;
-        if (x >= din) continue;
-        const int64_t idx = (((int64_t)vz * din + vy) * din + x) * 16 + n;
-        float v = acc[r];
-        if (accum) v += dx[idx];
-        if (mask && !(bf2f(mask[idx]) > 0.f)) v = 0.f;
-        dx[idx] = v;
-    }
-}
-
+// produced this conv's input) is given.  wt: [27][Cin][Cout].  Stride 1 runs
+// in conv3_s1_kernel (kernels_conv.hip).
 // Stride 2: dx[v] receives tap t only where v - d_t is even in every axis,
 // i.e. 1, 2, 4 or 8 taps by the parity class of v.  A wave takes 16 voxels of
 // one class along x (x = 2j + px, j = j0..j0+15, fixed y and z), so it runs
@@ -701,15 +655,7 @@ hipError_t conv_bwd_data(const float* dy, int dout, const uint16_t* w, const uin
                            dy, dout, wt, dx, din, accum ? 1 : 0, mask);
         return hipGetLastError();
     }
-    const int64_t tiles = (int64_t)din * din * ((din + 15) / 16);
-    const dim3 grid(blocks_for(tiles, 4));
-    if (stride == 1)
-        hipLaunchKernelGGL((conv_bwd_data_kernel<1>), grid, dim3(256), 0, s, dy, dout, wt, dx,
-                           din, accum ? 1 : 0, mask);
-    else
-        hipLaunchKernelGGL((conv_bwd_data_kernel<2>), grid, dim3(256), 0, s, dy, dout, wt, dx,
-                           din, accum ? 1 : 0, mask);
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 int wgrad_blocks(int dout)
