@@ -62,6 +62,8 @@ def _load():
     i64 = ctypes.c_int64
     lib.oracle_sweeps_f64.argtypes = [dp, dp, i64, i64, i64, i64, ctypes.c_int]
     lib.oracle_sweeps_f64.restype = ctypes.c_int
+    lib.oracle_sweeps27_f64.argtypes = [dp, dp, i64, i64, i64, i64, ctypes.c_int]
+    lib.oracle_sweeps27_f64.restype = ctypes.c_int
     lib.oracle_sweeps_f32.argtypes = [fp, fp, fp, i64, i64, i64, i64, ctypes.c_int]
     lib.oracle_sweeps_f32.restype = ctypes.c_int
     lib.oracle_residual_f64.argtypes = [dp, dp, i64, i64, i64, ctypes.c_int]
@@ -106,6 +108,25 @@ def sweeps_f64(box: np.ndarray, nsweeps: int, nthreads: int = 0) -> np.ndarray:
                                    nx, ny, nz, int(nsweeps), nt)
     if rc != 0:
         raise ValueError("oracle_sweeps_f64 rejected its arguments")
+    return a
+
+
+def sweeps27_f64(box: np.ndarray, nsweeps: int, nthreads: int = 0) -> np.ndarray:
+    """Return ``box`` after ``nsweeps`` sweeps of the 27-point Jacobi update
+    (faces, edges, corners weighted 14, 3, 1 over 128; the fold order is in
+    jacobi_oracle.c).  Not in the paper: one of the other stencils the
+    k-streaming pipeline carries.  The whole boundary layer, edges and corners
+    included, is read and kept."""
+    _check_box(box, np.float64)
+    a = np.array(box, dtype=np.float64, copy=True, order="C")
+    b = np.empty_like(a)
+    nx, ny, nz = _dims(a)
+    nt = nthreads if nthreads > 0 else max_threads()
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = _load().oracle_sweeps27_f64(a.ctypes.data_as(dp), b.ctypes.data_as(dp),
+                                     nx, ny, nz, int(nsweeps), nt)
+    if rc != 0:
+        raise ValueError("oracle_sweeps27_f64 rejected its arguments")
     return a
 
 

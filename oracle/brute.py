@@ -71,3 +71,41 @@ def residual(box):
                 s = s + float(box[k + 1, j, i])
                 r[k, j, i] = s - 6.0 * float(box[k, j, i])
     return r
+
+
+# 27-point Jacobi update (the definition and fold order of
+# jacobi_oracle.c's sweep27_f64), spelled per cell from offset lists.
+_W27 = (7.0 / 64.0, 3.0 / 128.0, 1.0 / 128.0)
+_CROSS = ((-1, 0), (1, 0), (0, -1), (0, 1))
+_DIAG = ((-1, -1), (1, -1), (-1, 1), (1, 1))
+
+
+def sweep27_f64(box):
+    nz2, ny2, nx2 = box.shape
+    a = [[[float(box[k, j, i]) for i in range(nx2)] for j in range(ny2)]
+         for k in range(nz2)]
+    out = np.array(box, dtype=np.float64, copy=True)
+
+    def fold(p, j, i, offs):
+        s = a[p][j + offs[0][1]][i + offs[0][0]]
+        for di, dj in offs[1:]:
+            s = s + a[p][j + dj][i + di]
+        return s
+
+    for k in range(1, nz2 - 1):
+        for j in range(1, ny2 - 1):
+            for i in range(1, nx2 - 1):
+                b = [fold(p, j, i, _CROSS) for p in (k - 1, k, k + 1)]
+                c = [fold(p, j, i, _DIAG) for p in (k - 1, k, k + 1)]
+                f = (b[1] + a[k - 1][j][i]) + a[k + 1][j][i]
+                e = (c[1] + b[0]) + b[2]
+                kk = c[0] + c[2]
+                out[k, j, i] = (_W27[0] * f + _W27[1] * e) + _W27[2] * kk
+    return out
+
+
+def sweeps27_f64(box, n):
+    out = np.array(box, dtype=np.float64, copy=True)
+    for _ in range(n):
+        out = sweep27_f64(out)
+    return out

@@ -195,6 +195,82 @@ double oracle_residual_norm_f64(const double *u, int64_t nx, int64_t ny,
 }
 
 /* Number of threads an OpenMP parallel region gets by default. */
+/* ------------------------------------------------------------------------
+ * 27-point Jacobi (not in the paper; one of the "other stencils" the k-
+ * streaming pipeline can carry).  The Jacobi update for the 27-point
+ * Laplacian with face, edge and corner weights 14, 3 and 1 over 128 (they
+ * sum to 1), with this fold order: per plane p at the cell's (i, j),
+ *   A(p) = x(i, j, p),
+ *   B(p) = ((x(i-1,j) + x(i+1,j)) + x(i,j-1)) + x(i,j+1),
+ *   C(p) = ((x(i-1,j-1) + x(i+1,j-1)) + x(i-1,j+1)) + x(i+1,j+1);
+ * then F = (B(k) + A(k-1)) + A(k+1)      (the 6 faces),
+ *      E = (C(k) + B(k-1)) + B(k+1)      (the 12 edges),
+ *      K = C(k-1) + C(k+1)               (the 8 corners),
+ *      u' = (W_F F + W_E E) + W_C K,  W_F = 7/64, W_E = 3/128, W_C = 1/128
+ * (dyadic, so the weights are exact).  The whole boundary layer (faces,
+ * edges and corners of the box) is read and passed through unchanged.
+ * ---------------------------------------------------------------------- */
+static const double W27_F = 7.0 / 64.0;
+static const double W27_E = 3.0 / 128.0;
+static const double W27_C = 1.0 / 128.0;
+
+static void sweep27_f64(const double *src, double *dst, int64_t nx, int64_t ny,
+                        int64_t nz, int nthreads)
+{
+    int64_t k;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (k = 0; k < nz + 2; ++k) {
+        for (int64_t j = 0; j < ny + 2; ++j) {
+            for (int64_t i = 0; i < nx + 2; ++i) {
+                int interior = (i >= 1 && i <= nx && j >= 1 && j <= ny &&
+                                k >= 1 && k <= nz);
+                if (!interior) {
+                    dst[IDX(i, j, k)] = src[IDX(i, j, k)];
+                    continue;
+                }
+                double a[3], b[3], c[3];
+                for (int d = 0; d < 3; ++d) {
+                    const int64_t p = k - 1 + d;
+                    a[d] = src[IDX(i, j, p)];
+                    double bs = src[IDX(i - 1, j, p)];
+                    bs = bs + src[IDX(i + 1, j, p)];
+                    bs = bs + src[IDX(i, j - 1, p)];
+                    bs = bs + src[IDX(i, j + 1, p)];
+                    b[d] = bs;
+                    double cs = src[IDX(i - 1, j - 1, p)];
+                    cs = cs + src[IDX(i + 1, j - 1, p)];
+                    cs = cs + src[IDX(i - 1, j + 1, p)];
+                    cs = cs + src[IDX(i + 1, j + 1, p)];
+                    c[d] = cs;
+                }
+                const double f = (b[1] + a[0]) + a[2];
+                const double e = (c[1] + b[0]) + b[2];
+                const double kk = c[0] + c[2];
+                dst[IDX(i, j, k)] = (W27_F * f + W27_E * e) + W27_C * kk;
+            }
+        }
+    }
+}
+
+int oracle_sweeps27_f64(double *a, double *b, int64_t nx, int64_t ny,
+                        int64_t nz, int64_t nsweeps, int nthreads)
+{
+    if (!a || !b || nx < 1 || ny < 1 || nz < 1 || nsweeps < 0)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    double *cur = a, *nxt = b;
+    for (int64_t s = 0; s < nsweeps; ++s) {
+        sweep27_f64(cur, nxt, nx, ny, nz, nthreads);
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    if (cur != a)
+        memcpy(a, cur, sizeof(double) * (size_t)((nx + 2) * (ny + 2) * (nz + 2)));
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
     return omp_get_max_threads();
