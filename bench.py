@@ -26,6 +26,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# FP64 vector issue peak for separate adds and multiplies (no fused
+# multiply-add): 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz, half of the
+# published 78.6 TFLOP/s, which counts an FMA as two operations.
+FP64_ADDMUL_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP64 adds and multiplies of one 27-point update (per interior cell and
+# sweep): plane sums 1 + 2 + 2, the three folds 2 + 2 + 1, weights 3 + 2, and
+# the two partial folds carried to the next plane 1 + 1 (the kernel's and the
+# oracle's fold order; 53 if the 26 neighbours were summed term by term).
+S27_OPS_PER_LUP = 16
 
 
 def parse():
@@ -61,7 +70,7 @@ DEFAULT_T = 5
 DEFAULT_LAYOUT = "ab"
 
 
-def time_steps(j, steps, sweeps, t, torch):
+def time_steps(j, steps, sweeps, t, torch, residual=True):
     """Time `steps` steps; per-trip HIP events give the trip-kernel duration."""
     stream = j.stream
     trips_per_step = []
@@ -87,7 +96,8 @@ def time_steps(j, steps, sweeps, t, torch):
                 ev.append((a, b))
             else:
                 j.sweep(L)
-        j.residual()
+        if residual:
+            j.residual()
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -274,9 +284,14 @@ def main():
                 w, _, tm, _ = run_config(n, sweeps, tt, lay, 1, 1, torch, box)
                 tab["%s_t%d" % (lay, tt)] = round(glups(n, sweeps, w), 1)
         extra["glups_by_layout_t_512"] = tab
+        extra["stencil27_512"] = bench_stencil27(torch, n, sweeps, box)
         if not args.quick:
             extra["n64_100_sweeps"] = bench_small_64(torch)
             extra["n1024"] = bench_1024(torch, t)
+            box1k = synth.sine_face_box(1024, 1024, 1024, seed=3)
+            extra["stencil27_1024"] = bench_stencil27(torch, 1024, 48, box1k,
+                                                      shapes=((3, 24, 3), (2, 36, 3)))
+            del box1k
             extra["teams_512"] = bench_teams(torch)
             extra["multigrid_time_to_1e-8_511"] = bench_multigrid_tts(torch, 511)
             extra["batched_256"] = bench_batched(torch)
@@ -315,6 +330,35 @@ def bench_1024(torch, t, sweeps=50):
         out[layout] = {"seg_len": info["seg_len"], "glups": round(g, 1),
                        "roofline_frac_spec": round(g / (HBM_PEAK_GBS * t / 16.0), 4)}
     del box
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_stencil27(torch, n, sweeps, box, shapes=((2, 36, 3), (3, 24, 3), (4, 24, 3))):
+    """27-point A/B FP64 sweeps of the n^3 box for each tile shape (t, tile
+    rows, rows per wave): GLUP/s over `sweeps` sweeps after a warm-up trip,
+    and the roofline of the trip kernel from per-trip HIP events on the
+    solver's stream.  The kernel is bound by FP64 vector issue (16 adds and
+    multiplies per cell and sweep, see S27_OPS_PER_LUP), not by HBM (16 B per
+    cell and trip)."""
+    from paper_1006_3148_amd import Jacobi
+    out = {"n": n, "sweeps": sweeps, "ops_per_lup": S27_OPS_PER_LUP}
+    for t, rows, rpw in shapes:
+        j = Jacobi(box, t=t, layout="ab", tile_rows=rows, rows_per_wave=rpw, stencil=27)
+        j.sweep(t)
+        j.sync()
+        wall, _, trip_ms, _ = time_steps(j, 1, sweeps, t, torch, residual=False)
+        j.close()
+        del j
+        ms = sum(trip_ms) / len(trip_ms)
+        tops = S27_OPS_PER_LUP * n ** 3 * t / (ms * 1e-3) / 1e12
+        gbs = 16.0 * n ** 3 / (ms * 1e-3) / 1e9
+        out["t%d_%dx%d" % (t, rows // rpw, rpw)] = {
+            "glups": round(glups(n, sweeps, wall), 1),
+            "roofline": {"bound": "alu", "achieved": round(tops, 3),
+                         "peak": round(FP64_ADDMUL_PEAK_TOPS, 2), "unit": "TFLOP/s",
+                         "frac": round(tops / FP64_ADDMUL_PEAK_TOPS, 4),
+                         "launch_ms": round(ms, 4), "hbm_alg_GBs": round(gbs, 1)}}
     torch.cuda.empty_cache()
     return out
 

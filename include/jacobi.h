@@ -23,6 +23,18 @@
  * fl(1/6); IEEE round-to-nearest, no fused multiply-add.  FP64 results are
  * bitwise identical for every t, layout and tile shape.
  *
+ * 27-point update (jacobi_desc.stencil = 27; not in the paper, another
+ * stencil on the same k-streaming pipeline): the weighted mean of the 26
+ * neighbours, 7/64 for each of the 6 faces, 3/128 for each of the 12 edges
+ * and 1/128 for each of the 8 corners (the weights sum to 1).  With, for
+ * plane p of the 3x3 window of A around (i,j), a(p) the centre, b(p) the left
+ * fold of (i-1,j), (i+1,j), (i,j-1), (i,j+1) and c(p) that of (i-1,j-1),
+ * (i+1,j-1), (i-1,j+1), (i+1,j+1):
+ *     B[i,j,k] = (7/64 ((b(k) + a(k-1)) + a(k+1))
+ *                 + 3/128 ((c(k) + b(k-1)) + b(k+1)))
+ *                + 1/128 (c(k-1) + c(k+1)),
+ * bitwise identical for every t and tile shape.
+ *
  * Memory: every device buffer is owned by the caller (e.g. allocated with
  * PyTorch); the library allocates no device memory and owns only the host
  * handle (and the static reduction array of jacobi_residual_noalloc).  Box layout: element (i,j,k) of a frame with origin O and strides
@@ -112,6 +124,12 @@ typedef struct {
     void *workspace;     /* device scratch owned by the caller */
     size_t workspace_bytes;
     void *stream;        /* hipStream_t (NULL = default stream) */
+    int32_t stencil;     /* 0 or 7: Eq. (1); 27: the 27-point Jacobi update
+                            (below), FP64 and the AB layout only, teams <= 1,
+                            t in 1..4; t = 0 autotunes as above among the
+                            27-point candidates (t = 2 until then);
+                            jacobi_residual and jacobi_solve return
+                            JACOBI_EUNSUPPORTED */
 } jacobi_desc;
 
 typedef struct jacobi_s jacobi_t;
@@ -159,7 +177,7 @@ int jacobi_create(const jacobi_desc *d, jacobi_t **out);
 int jacobi_sweep(jacobi_t *h, int64_t n_steps);
 
 /* ||fold(u nbrs) - 6u||_2 over the interior of the current iterate, FP64,
- * deterministic fixed-order reduction.  Synchronizes the stream; reports a
+ * deterministic fixed-order reduction (7-point handles only).  Synchronizes the stream; reports a
  * pending kernel fault (JACOBI_EHIP) or watchdog time-out (JACOBI_ETIMEOUT).
  * Optional `maxabs` receives max |r|. */
 int jacobi_residual(jacobi_t *h, double *l2, double *maxabs);

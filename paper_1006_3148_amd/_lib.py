@@ -54,7 +54,7 @@ class JacobiDesc(ctypes.Structure):
         ("teams", ctypes.c_int32), ("looseness", ctypes.c_int32),
         ("grid0", ctypes.c_void_p), ("grid1", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-        ("stream", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p), ("stencil", ctypes.c_int32),
     ]
 
 

@@ -63,6 +63,7 @@ struct TripParams {
                                 // (planes, >= T)
     int krev;                   // mode 1, dir -1: src/dst are k-mirrored
                                 // views (origin at plane nz+1, py < 0)
+    int s27;                    // mode 0 FP64: the 27-point update
 };
 
 // Claim groups of a compressed-grid launch (one per XCD).
@@ -82,6 +83,8 @@ hipError_t launch_trip_f64(const TripConfig& cfg, const TripParams& p,
 hipError_t launch_trip_f32(const TripConfig& cfg, const TripParams& p,
                            hipStream_t s);
 bool trip_config_supported(int dtype_f32, const TripConfig& cfg);
+// Tile shapes compiled for the 27-point update (FP64, A/B).
+bool trip_config_supported_s27(const TripConfig& cfg);
 
 // ---- auxiliary kernels (kernels_aux.hip) ----
 hipError_t launch_fill_i32(int* p, int value, int64_t n, hipStream_t s);

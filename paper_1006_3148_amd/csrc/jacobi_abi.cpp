@@ -49,8 +49,16 @@ int hip_fail(hipError_t e, const char* what)
 // Tile shape (rows per wave, waves) per T: the fastest shape measured on a
 // 512^3 FP64 box.  The compressed grid's persistent tiles are fastest with 4
 // rows x 8 waves at every T.
-TripConfig default_cfg(int T, bool compressed)
+TripConfig default_cfg(int T, bool compressed, bool s27)
 {
+    if (s27) {
+        switch (T) {
+        case 1: return TripConfig{1, 4, 8};
+        case 2: return TripConfig{2, 3, 12};
+        case 3: return TripConfig{3, 3, 8};
+        default: return TripConfig{T, 3, 8};
+        }
+    }
     if (compressed) return TripConfig{T, 4, 8};
     switch (T) {
     case 1:
@@ -213,6 +221,26 @@ constexpr int64_t kTuneSweeps = 96;  // >= 3 trips of every candidate
 constexpr int kTuneDefaultT = 5;
 
 constexpr int kMaxTeams = 1024;
+// 27-point handles: the largest t compiled, the autotuner's candidates and
+// the t used until the tuning has run.
+constexpr int kS27MaxT = 4;
+const TripConfig kS27TuneCandidates[] = {{2, 3, 12}, {2, 4, 8}, {3, 3, 8}, {4, 3, 8}};
+constexpr int kS27DefaultT = 2;
+
+struct Candidates {
+    const TripConfig* c;
+    int n;
+};
+Candidates tune_candidates(bool s27)
+{
+    if (s27)
+        return {kS27TuneCandidates, (int)(sizeof kS27TuneCandidates / sizeof(TripConfig))};
+    return {kTuneCandidates, (int)(sizeof kTuneCandidates / sizeof(TripConfig))};
+}
+bool config_supported(bool s27, const TripConfig& c)
+{
+    return s27 ? trip_config_supported_s27(c) : trip_config_supported(0, c);
+}
 
 // Extra shift along k of a compressed trip (planes).  A forward trip of L
 // sweeps stores its result shifted by (-L, -L, -L-E) (a backward trip by
@@ -265,12 +293,22 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                     (long long)d->nx, (long long)d->ny, (long long)d->nz);
     if (d->layout != JACOBI_LAYOUT_AB && d->layout != JACOBI_LAYOUT_COMPRESSED)
         return fail(JACOBI_EINVAL, "unknown layout %d", d->layout);
+    if (d->stencil != 0 && d->stencil != 7 && d->stencil != 27)
+        return fail(JACOBI_EINVAL, "stencil must be 0, 7 or 27 (got %d)", d->stencil);
+    const bool s27 = d->stencil == 27;
+    if (s27 && (d->dtype != JACOBI_F64 || d->layout != JACOBI_LAYOUT_AB || d->teams > 1))
+        return fail(JACOBI_EUNSUPPORTED,
+                    "the 27-point update needs FP64, the AB layout and teams <= 1");
     const bool tune = d->t == 0 && d->layout == JACOBI_LAYOUT_AB && d->dtype == JACOBI_F64 &&
                       d->tile_rows == 0 && d->rows_per_wave == 0 && d->seg_len == 0;
-    const int t = mg ? kMgT : d->t == 0 ? (tune ? kTuneMaxT : 4) : d->t;
-    if (t < 1 || t > 8)
-        return fail(JACOBI_EUNSUPPORTED,
-                    "sweeps per trip t=%d not supported (1..8)", t);
+    const int t = mg                ? kMgT
+                  : d->t != 0       ? d->t
+                  : tune            ? (s27 ? kS27MaxT : kTuneMaxT)
+                  : s27             ? kS27DefaultT
+                                    : 4;
+    if (t < 1 || t > (s27 ? kS27MaxT : 8))
+        return fail(JACOBI_EUNSUPPORTED, "sweeps per trip t=%d not supported (1..%d)", t,
+                    s27 ? kS27MaxT : 8);
     if (d->inner_sweeps < 0) return fail(JACOBI_EINVAL, "inner_sweeps < 0");
     if (d->teams < 0 || d->teams > kMaxTeams)
         return fail(JACOBI_EINVAL, "teams must be in 0..%d", kMaxTeams);
@@ -286,7 +324,7 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
         return fail(JACOBI_EINVAL, "one k-plane must be < 2 GiB");
     int64_t max_tiles = 0;
     for (int T = 1; T <= t; ++T) {
-        TripConfig cfg = default_cfg(T, comp);
+        TripConfig cfg = default_cfg(T, comp, s27);
         if (T == t && !mg && (d->tile_rows > 0 || d->rows_per_wave > 0)) {
             const int R = d->rows_per_wave > 0 ? d->rows_per_wave : 4;
             const int rows = d->tile_rows > 0 ? d->tile_rows : cfg.R * cfg.W;
@@ -294,7 +332,8 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                 return fail(JACOBI_EINVAL, "tile_rows must be a multiple of rows_per_wave");
             cfg = TripConfig{T, R, rows / R};
         }
-        if (!trip_config_supported(d->dtype != JACOBI_F64, cfg))
+        if (s27 ? !trip_config_supported_s27(cfg)
+                : !trip_config_supported(d->dtype != JACOBI_F64, cfg))
             return fail(JACOBI_EUNSUPPORTED,
                         "tile shape t=%d rows=%d rows_per_wave=%d is not compiled",
                         T, cfg.R * cfg.W, cfg.R);
@@ -307,9 +346,11 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
         max_tiles = std::max<int64_t>(max_tiles, plans[T].ntiles);
     }
     if (tune) {
-        for (const TripConfig& c : kTuneCandidates) {
+        const Candidates cs = tune_candidates(s27);
+        for (int q = 0; q < cs.n; ++q) {
+            const TripConfig& c = cs.c[q];
             Plan pl;
-            if (trip_config_supported(0, c) &&
+            if (config_supported(s27, c) &&
                 make_plan(d->nx, d->ny, d->nz, c, 0, false, kCUs, &pl))
                 max_tiles = std::max<int64_t>(max_tiles, pl.ntiles);
         }
@@ -384,6 +425,7 @@ hipError_t launch_trip(jacobi_t* h, int T, bool f32, const void* src, void* dst,
     if (mode == 0 && h->ab_bands && pl.ntiles > kCUs) p.chunk = 1;  // band order (band_tile)
     p.zshift = zshift > 0 ? zshift : T;
     p.krev = krev ? 1 : 0;
+    p.s27 = h->d.stencil == 27 ? 1 : 0;
     p.err = h->err;
     p.spin_limit = h->spin_limit;
     p.teams = teams;
@@ -459,7 +501,7 @@ int run_f64(jacobi_t* h, int64_t n)
             e = launch_trip(h, h->t, false, grid_origin(h, h->cur),
                             grid_origin(h, 1 - h->cur), nullptr, h->px, h->py, 3, 1, k);
             h->cur ^= (k & 1);
-        } else if (h->d.layout == JACOBI_LAYOUT_AB && L == 1 &&
+        } else if (h->d.layout == JACOBI_LAYOUT_AB && L == 1 && h->d.stencil != 27 &&
                    h->d.nx * h->d.ny * h->d.nz <= kSmallBoxCells) {
             e = launch_sweep1_f64(grid_origin(h, h->cur), grid_origin(h, 1 - h->cur), h->px,
                                   h->py, (int)h->d.nx, (int)h->d.ny, (int)h->d.nz, h->run);
@@ -664,10 +706,13 @@ int autotune_single(jacobi_t* h, int64_t* n)
     const double cells = (double)h->d.nx * h->d.ny * h->d.nz;
     double best = -1;
     Plan best_plan = h->plans[h->t];
-    for (const TripConfig& c : kTuneCandidates) {
+    const bool s27 = h->d.stencil == 27;
+    const Candidates cs = tune_candidates(s27);
+    for (int q = 0; q < cs.n; ++q) {
+        const TripConfig& c = cs.c[q];
         if (e != hipSuccess) break;
         Plan pl;
-        if (!trip_config_supported(0, c) ||
+        if (!config_supported(s27, c) ||
             !make_plan(h->d.nx, h->d.ny, h->d.nz, c, 0, false, kCUs, &pl))
             continue;
         const Plan saved = h->plans[c.T];
@@ -797,9 +842,10 @@ int jacobi_create(const jacobi_desc* d, jacobi_t** out)
     if (!h) return fail(JACOBI_EINVAL, "out of host memory");
     h->d = *d;
     h->t = t;
-    if (d->t == 0 && t == kTuneMaxT) {
+    const bool s27 = d->stencil == 27;
+    if (d->t == 0 && t == (s27 ? kS27MaxT : kTuneMaxT)) {
         h->tune_pending = true;
-        h->t = kTuneDefaultT;
+        h->t = s27 ? kS27DefaultT : kTuneDefaultT;
     }
     for (int T = 1; T <= t; ++T) h->plans[T] = plans[T];
     const bool comp = d->layout == JACOBI_LAYOUT_COMPRESSED;
@@ -926,6 +972,8 @@ int jacobi_sweep(jacobi_t* h, int64_t n_steps)
 int jacobi_residual(jacobi_t* h, double* l2, double* maxabs)
 {
     if (!h || !l2) return fail(JACOBI_EINVAL, "null argument");
+    if (h->d.stencil == 27)
+        return fail(JACOBI_EUNSUPPORTED, "the residual is that of the 7-point equation");
     const AuxProblem& a = aux_view(h);
     hipError_t e = launch_residual_tab(nullptr, 1, a, nullptr, a.rblocks,
                                        h->partials, h->red_out, h->stream);

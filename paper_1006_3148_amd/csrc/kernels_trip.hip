@@ -12,6 +12,7 @@ hipError_t trip_dispatch_f64_m1(const TripConfig&, const TripParams&, hipStream_
 hipError_t trip_dispatch_f64_m1r(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f64_m2(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f64_m3(const TripConfig&, const TripParams&, hipStream_t);
+hipError_t trip_dispatch_f64_s27(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f32_m0(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f32_m2(const TripConfig&, const TripParams&, hipStream_t);
 hipError_t trip_dispatch_f32rhs_m0(const TripConfig&, const TripParams&, hipStream_t);
@@ -28,9 +29,19 @@ bool trip_config_supported(int dtype_f32, const TripConfig& c)
     return false;
 }
 
+bool trip_config_supported_s27(const TripConfig& c)
+{
+#define JACOBI_SUP(T_, R_, W_) \
+    if (c.T == T_ && c.R == R_ && c.W == W_) return true;
+    JACOBI_S27_CFGS(JACOBI_SUP)
+#undef JACOBI_SUP
+    return false;
+}
+
 hipError_t launch_trip_f64(const TripConfig& c, const TripParams& p,
                            hipStream_t s)
 {
+    if (p.s27) return p.mode == 0 ? trip_dispatch_f64_s27(c, p, s) : hipErrorInvalidValue;
     switch (p.mode) {
     case 0: return trip_dispatch_f64_m0(c, p, s);
     case 1: return p.krev ? trip_dispatch_f64_m1r(c, p, s) : trip_dispatch_f64_m1(c, p, s);

@@ -23,8 +23,8 @@ struct Plan {
 };
 
 // Default tile shape for T sweeps per trip (register state fits without
-// spilling; measured best on MI355X at 512^3).
-TripConfig default_cfg(int T, bool compressed = false);
+// spilling; measured best on MI355X at 512^3); s27: of the 27-point update.
+TripConfig default_cfg(int T, bool compressed = false, bool s27 = false);
 
 // Tiling of one (nx, ny, nz) box for `cfg`.  seg_req > 0 fixes the k segment
 // length; `compressed` enforces tiles and segments >= 2T (the shift safety

@@ -11,3 +11,9 @@
     X(7, 2, 16) X(8, 2, 16) X(7, 4, 8) X(8, 4, 8)                             \
     X(2, 4, 12) X(3, 3, 12) X(4, 3, 12) X(4, 4, 12) X(5, 3, 12) X(5, 4, 12)   \
     X(6, 3, 12) X(3, 4, 12)
+
+// Tile shapes of the 27-point update (FP64, A/B): six FP64 values of
+// k-streaming state per stage and cell instead of two, so fewer stages fit in
+// the registers of a 512-thread workgroup.
+#define JACOBI_S27_CFGS(X) \
+    X(1, 4, 8) X(2, 4, 8) X(2, 3, 12) X(2, 2, 16) X(3, 3, 8) X(3, 4, 8) X(4, 3, 8)

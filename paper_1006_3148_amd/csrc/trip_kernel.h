@@ -111,11 +111,23 @@ struct Xch {
 // their stores, like a forward trip's, land behind the stream.  Logical plane
 // q+1 is then physical k-1, and the update keeps Eq. (1)'s order (k-1 before
 // k+1) by holding one more plane per stage.
+// S27: the 27-point Jacobi update instead of Eq. (1) (A/B sweeps only): the
+// mean of the 26 neighbours weighted 7/64 (6 faces), 3/128 (12 edges) and
+// 1/128 (8 corners), from per-plane partial sums of the 3x3 window of plane
+// p: A(p) the centre, B(p) the four in-plane faces (i-1, i+1, j-1, j+1), C(p)
+// the four in-plane corners ((i-1,j-1), (i+1,j-1), (i-1,j+1), (i+1,j+1)),
+// each a left fold in that order; the update of plane q-1 is
+//   (7/64 ((B(q-1) + A(q-2)) + A(q)) + 3/128 ((C(q-1) + B(q-2)) + B(q)))
+//     + 1/128 (C(q-2) + C(q)).
+// The window moves along k like the 7-point one: a stage keeps, per cell,
+// the folds started by planes q-1 and q-2 and the three sums of plane q-1.
 template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE,
-          bool WT = false, bool KREV = false>
+          bool WT = false, bool KREV = false, bool S27 = false>
 __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int tile,
                                          Real (*xch)[T][W][2][64])
 {
+    static_assert(!S27 || (!RHS && !FLAGS && !WT && !KREV && R >= 2),
+                  "the 27-point update is built for plain A/B sweeps with R >= 2");
     constexpr int H = R * W;
     constexpr int OX = 64 - 2 * T;
     constexpr int OY = H - 2 * T;
@@ -198,7 +210,12 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     // completed.  P, C: per-stage k-streaming state (partial sum, and the
     // plane consumed in the previous step).
     // KREV: P holds the in-plane sum alone and D the plane before C.
+    // S27: P holds the face fold B(q-1) + A(q-2) and C the centre A(q-1);
+    // EP the edge fold C(q-1) + B(q-2), KP the corner sum C(q-2), BP and CP
+    // the sums B(q-1) and C(q-1).
+    constexpr int S27N = S27 ? T : 1;
     Real X[T + 1][R], P[T][R], C[T][R], D[KREV ? T : 1][R];
+    Real EP[S27N][R], KP[S27N][R], BP[S27N][R], CP[S27N][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
@@ -208,6 +225,13 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
             P[s][r] = Real(0);
             C[s][r] = Real(0);
             if (KREV) D[KREV ? s : 0][r] = Real(0);
+        }
+#pragma unroll
+        for (int s = 0; s < S27N; ++s) {
+            EP[s][r] = Real(0);
+            KP[s][r] = Real(0);
+            BP[s][r] = Real(0);
+            CP[s][r] = Real(0);
         }
     }
     // rr[m]: rhs plane a+n-1-m; stage s+1 completes plane a+n-2s-1 and takes
@@ -333,6 +357,73 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
             C[s][r] = xo;
             return e;
         };
+
+        // 27-point update of row r from the row above (j-1: its value and
+        // the sum of its i-neighbours) and the row below (j+1: its i-1 and
+        // i+1 neighbours), with hs the sum of row r's own i-neighbours.
+        auto update27 = [&](const int s, const int r, const Real above, const Real habove,
+                            const Real below, const Real lbelow, const Real rbelow,
+                            const Real hs) {
+            const int pe = a + n - 2 * s - 1;
+            const bool bnd = BND && ((pe == 0) || (pe == g.nz + 1));
+            const int s2 = S27 ? s : 0;
+            const Real xo = X[s][r];
+            const Real bq = (hs + above) + below;
+            const Real cq = (habove + lbelow) + rbelow;
+            Real e;
+            if (bnd) {
+                e = C[s][r];
+            } else {
+                const Real wf = Real(7) / Real(64), we = Real(3) / Real(128),
+                           wc = Real(1) / Real(128);
+                e = (wf * (P[s][r] + xo) + we * (EP[s2][r] + bq)) + wc * (KP[s2][r] + cq);
+                if (EDGE) e = (lane_int && row_int[r]) ? e : C[s][r];
+            }
+            P[s][r] = bq + C[s][r];
+            EP[s2][r] = cq + BP[s2][r];
+            KP[s2][r] = CP[s2][r];
+            C[s][r] = xo;
+            BP[s2][r] = bq;
+            CP[s2][r] = cq;
+            return e;
+        };
+
+        if constexpr (S27) {
+            // i-neighbours of every row of every stage's input (lane shifts),
+            // then rows 1..R-2 before the barrier as below.
+            Real LX[T][R], RX[T][R], HX[T][R];
+            Real Y[T][R > 2 ? R - 2 : 1];
+#pragma unroll
+            for (int s = T - 1; s >= 0; --s) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    LX[s][r] = from_left(X[s][r]);
+                    RX[s][r] = from_right(X[s][r]);
+                    HX[s][r] = LX[s][r] + RX[s][r];
+                }
+#pragma unroll
+                for (int r = 1; r + 1 < R; ++r)
+                    Y[s][r - 1] = update27(s, r, X[s][r - 1], HX[s][r - 1], X[s][r + 1],
+                                           LX[s][r + 1], RX[s][r + 1], HX[s][r]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = T - 1; s >= 0; --s) {
+                const Real up = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+                const Real dn = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+                const Real hup = from_left(up) + from_right(up);
+                const Real e0 = update27(s, 0, up, hup, X[s][1], LX[s][1], RX[s][1], HX[s][0]);
+                const Real e1 = update27(s, R - 1, X[s][R - 2], HX[s][R - 2], dn,
+                                         from_left(dn), from_right(dn), HX[s][R - 1]);
+                X[s + 1][0] = e0;
+                X[s + 1][R - 1] = e1;
+#pragma unroll
+                for (int r = 1; r + 1 < R; ++r) X[s + 1][r] = Y[s][r - 1];
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            return;
+        }
 
         // Rows 1..R-2 of every stage need nothing from the other waves:
         // computed before the barrier (into Y, since X[s] rows are still read
@@ -507,7 +598,7 @@ __device__ __forceinline__ void finish_team(const TripParams& p, int tile, int t
 //         so every item an item waits for has a smaller ticket (no
 //         deadlock, whatever number of workgroups is resident).
 template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false,
-          bool KREV = false>
+          bool KREV = false, bool S27 = false>
 __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
 {
     constexpr bool FLAGS = MODE == 1;
@@ -602,21 +693,21 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
             wait_team(p.flags, p.done, p.err, p.tiles_x, p.tiles_y, p.segs, p.ntiles,
                       p.looseness, p.spin_limit, tile, team);
         if (interior_tile)
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, false, WT, KREV>(p, g, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, false, WT, KREV, S27>(p, g, tile, xch);
         else
-            run_tile<Real, T, R, W, PF, RHS, FLAGS, true, WT, KREV>(p, g, tile, xch);
+            run_tile<Real, T, R, W, PF, RHS, FLAGS, true, WT, KREV, S27>(p, g, tile, xch);
         if (MODE == 3) finish_team(p, tile, team);
     }
 }
 
 // Launches one trip in MODE with tile shape (T, R, W).
 template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false,
-          bool KREV = false>
+          bool KREV = false, bool S27 = false>
 hipError_t launch_mode(const TripParams& p, hipStream_t s)
 {
     const dim3 block(64 * W);
     if constexpr (MODE == 0) {
-        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 0, WT>),
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 0, WT, false, S27>),
                            dim3(p.ntiles), block, 0, s, p);
         return hipGetLastError();
     }
@@ -628,7 +719,7 @@ hipError_t launch_mode(const TripParams& p, hipStream_t s)
     if (e == hipSuccess)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu,
-            reinterpret_cast<const void*>(&trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, KREV>),
+            reinterpret_cast<const void*>(&trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, KREV, S27>),
             64 * W, 0);
     if (e != hipSuccess) return e;
     int grid = cus * (per_cu > 0 ? per_cu : 1);
@@ -643,8 +734,8 @@ hipError_t launch_mode(const TripParams& p, hipStream_t s)
         else
             q.chunk = grid >= items ? 0 : grid / kClaimGroups;
     }
-    hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, KREV>), dim3(grid), block,
-                       0, s, q);
+    hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, KREV, S27>), dim3(grid),
+                       block, 0, s, q);
     return hipGetLastError();
 }
 

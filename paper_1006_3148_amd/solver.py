@@ -46,7 +46,7 @@ class Jacobi:
                  inner_sweeps: int = 0, tile_rows: int = 0,
                  rows_per_wave: int = 0, seg_len: int = 0, stream=None,
                  device: str = "cuda", use_graph: bool = False, teams: int = 0,
-                 looseness: int = -1):
+                 looseness: int = -1, stencil: int = 7):
         if isinstance(box, np.ndarray):
             box_t = torch.from_numpy(np.ascontiguousarray(box, dtype=np.float64))
         else:
@@ -69,6 +69,7 @@ class Jacobi:
         d.use_graph = 1 if use_graph else 0
         d.teams = teams
         d.looseness = looseness
+        d.stencil = stencil
         self.layout = layout
         gb = ctypes.c_size_t()
         check(lib.jacobi_grid_bytes(ctypes.byref(d), ctypes.byref(gb)))

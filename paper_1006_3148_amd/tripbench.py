@@ -35,6 +35,7 @@ def main(argv=None):
     ap.add_argument("--teams", type=int, default=0)
     ap.add_argument("--looseness", type=int, default=-1)
     ap.add_argument("--seg-len", type=int, default=0, help="k planes per segment (0 = auto)")
+    ap.add_argument("--stencil", type=int, default=7, help="7 or 27 (27-point update)")
     a = ap.parse_args(argv)
     import torch
     import synth
@@ -45,7 +46,7 @@ def main(argv=None):
         sweeps = a.sweeps if a.sweeps > 0 else 4 * t
         j = Jacobi(box, t=t, layout=a.layout, dtype=a.dtype, tile_rows=a.tile_rows,
                    rows_per_wave=a.rows_per_wave, teams=a.teams, looseness=a.looseness,
-                   seg_len=a.seg_len)
+                   seg_len=a.seg_len, stencil=a.stencil)
         j.sweep(sweeps)
         j.sync()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -58,6 +59,7 @@ def main(argv=None):
         info = j.info()
         j.close()
         print(json.dumps({"n": a.n, "t": t, "layout": a.layout, "dtype": a.dtype,
+                          "stencil": a.stencil, "rows_per_wave": a.rows_per_wave,
                           "sweeps_per_call": sweeps, "tile_rows": info["tile_rows"],
                           "seg_len": info["seg_len"], "ms_per_call": round(ms, 4),
                           "glups": round(a.n ** 3 * sweeps / (ms * 1e-3) / 1e9, 1)}),

@@ -86,6 +86,12 @@ def _rc(fn, *args):
     (dict(inner_sweeps=-3), -1),
     (dict(tile_rows=33, rows_per_wave=4), -1),
     (dict(tile_rows=24, rows_per_wave=4), -2),
+    (dict(stencil=5), -1),
+    (dict(stencil=27, dtype=1), -2),
+    (dict(stencil=27, layout=1), -2),
+    (dict(stencil=27, teams=2), -2),
+    (dict(stencil=27, t=5), -2),
+    (dict(stencil=27, t=3, tile_rows=48, rows_per_wave=4), -2),
 ])
 def test_bad_descriptors_are_rejected(kw, code):
     from paper_1006_3148_amd import lib
@@ -96,6 +102,19 @@ def test_bad_descriptors_are_rejected(kw, code):
     assert lib.jacobi_create(ctypes.byref(d), ctypes.byref(h)) == code
     assert h.value is None
     assert lib.jacobi_last_error().decode() != ""
+
+
+def test_stencil27_descriptors_plan_without_a_gpu():
+    from paper_1006_3148_amd import lib
+    n = ctypes.c_size_t()
+    for t in (0, 1, 2, 3, 4):
+        d = _desc(dims=(100, 70, 30), stencil=27, t=t)
+        assert lib.jacobi_workspace_size(ctypes.byref(d), ctypes.byref(n)) == 0
+    # every compiled 27-point shape is accepted for its t
+    for t, rows, rpw in ((1, 32, 4), (2, 32, 4), (2, 36, 3), (2, 32, 2), (3, 24, 3),
+                         (3, 32, 4), (4, 24, 3)):
+        d = _desc(dims=(100, 70, 30), stencil=27, t=t, tile_rows=rows, rows_per_wave=rpw)
+        assert lib.jacobi_workspace_size(ctypes.byref(d), ctypes.byref(n)) == 0, (t, rows)
 
 
 def test_create_checks_buffers_before_touching_the_gpu():
