@@ -287,11 +287,12 @@ def main():
         extra["stencil27_512"] = bench_stencil27(torch, n, sweeps, box)
         if not args.quick:
             extra["n64_100_sweeps"] = bench_small_64(torch)
-            extra["n1024"] = bench_1024(torch, t)
-            box1k = synth.sine_face_box(1024, 1024, 1024, seed=3)
+            box1k = torch.from_numpy(synth.sine_face_box(1024, 1024, 1024, seed=3)).cuda()
+            extra["n1024"] = bench_1024(torch, t, box1k)
             extra["stencil27_1024"] = bench_stencil27(torch, 1024, 48, box1k,
                                                       shapes=((3, 24, 3), (2, 36, 3)))
             del box1k
+            torch.cuda.empty_cache()
             extra["teams_512"] = bench_teams(torch)
             extra["multigrid_time_to_1e-8_511"] = bench_multigrid_tts(torch, 511)
             extra["batched_256"] = bench_batched(torch)
@@ -305,13 +306,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_1024(torch, t, sweeps=50):
-    """1024^3 interior, sine-mode faces: the compressed single grid (8.6 GB
-    plus shift planes) and the A/B layout (17.2 GB), GLUP/s of `sweeps`
-    sweeps after a warm-up trip."""
-    import synth
+def bench_1024(torch, t, box, sweeps=50):
+    """1024^3 interior, sine-mode faces (`box`, on the GPU): the compressed
+    single grid (8.6 GB plus shift planes) and the A/B layout (17.2 GB),
+    GLUP/s of `sweeps` sweeps after a warm-up trip."""
     from paper_1006_3148_amd import Jacobi
-    box = torch.from_numpy(synth.sine_face_box(1024, 1024, 1024, seed=3)).cuda()
     out = {"sweeps": sweeps, "t": t}
     for layout in ("compressed", "ab"):
         j = Jacobi(box, t=t, layout=layout)
@@ -329,8 +328,6 @@ def bench_1024(torch, t, sweeps=50):
         g = 1024 ** 3 * sweeps / dt / 1e9
         out[layout] = {"seg_len": info["seg_len"], "glups": round(g, 1),
                        "roofline_frac_spec": round(g / (HBM_PEAK_GBS * t / 16.0), 4)}
-    del box
-    torch.cuda.empty_cache()
     return out
 
 
