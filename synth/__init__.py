@@ -19,6 +19,7 @@ drawn is part of the definition of each input.
 
 from .grids import (  # noqa: F401
     uniform_box,
+    full_random_box,
     sine_face_box,
     sine_face_modes,
     sine_faces,

@@ -45,6 +45,16 @@ def uniform_box(nx: int, ny: int, nz: int, seed: int,
     return box.astype(dtype, copy=False)
 
 
+def full_random_box(nx: int, ny: int, nz: int, seed: int,
+                    dtype=np.float64) -> np.ndarray:
+    """Every cell U[0,1): interior, faces, and the edges and corners of the
+    boundary layer (which a 27-point update reads).
+
+    Draw order: one ``rng.random((nz+2, ny+2, nx+2))`` for the whole box.
+    """
+    return _rng(seed).random((nz + 2, ny + 2, nx + 2)).astype(dtype, copy=False)
+
+
 # Faces in this fixed order: i=0, i=nx+1, j=0, j=ny+1, k=0, k=nz+1.
 FACES = ("i0", "i1", "j0", "j1", "k0", "k1")
 

@@ -65,6 +65,20 @@ def test_compressed_trips_bitwise(t, dims):
     _assert_same(got, want, "compressed t=%d %s" % (t, dims))
 
 
+@pytest.mark.parametrize("layout", ["ab", "compressed"])
+@pytest.mark.parametrize("t", [1, 3, 5, 8])
+@pytest.mark.parametrize("dims", [(70, 45, 37), (2, 3, 1)])
+def test_full_random_box_bitwise(layout, t, dims):
+    """Every cell random: a nonzero starting interior, and edges and corners of
+    the boundary layer that the 7-point update never reads but must pass
+    through unchanged."""
+    box = synth.full_random_box(*dims, seed=500 + t)
+    n = 2 * t + 1
+    print("case full random %s t=%d dims=%s n=%d" % (layout, t, dims, n), flush=True)
+    got, _ = _run(box, n, t=t, layout=layout)
+    _assert_same(got, oracle.sweeps_f64(box, n), "full random %s t=%d %s" % (layout, t, dims))
+
+
 @pytest.mark.parametrize("t,dims,seg_len", [
     (5, (70, 45, 37), 0),       # E = 2t, one k segment
     (5, (130, 67, 90), 30),     # E = 2t, three segments of 30 planes

@@ -47,6 +47,19 @@ def test_s27_trips_bitwise(t, dims):
     _assert_same(got, oracle.sweeps27_f64(box, n), "s27 t=%d %s" % (t, dims))
 
 
+@pytest.mark.parametrize("t", [1, 2, 3, 4])
+@pytest.mark.parametrize("dims", [(70, 45, 37), (1, 1, 1), (2, 3, 1), (130, 67, 21)])
+def test_s27_full_random_box_bitwise(t, dims):
+    """Every cell random, the edges and corners of the boundary layer and the
+    interior included: the update reads the box's edges and corners, which
+    the boundary-only boxes above hold at zero."""
+    box = synth.full_random_box(*dims, seed=340 + t)
+    n = 2 * t + 1
+    print("case s27 full random t=%d dims=%s n=%d" % (t, dims, n), flush=True)
+    got, _ = _run(box, [n], t=t)
+    _assert_same(got, oracle.sweeps27_f64(box, n), "s27 full random t=%d %s" % (t, dims))
+
+
 SHAPES = [(1, 32, 4), (2, 32, 4), (2, 36, 3), (2, 32, 2), (3, 24, 3), (3, 32, 4),
           (4, 24, 3)]
 
@@ -126,4 +139,17 @@ def test_s27_512cube_bitwise(t):
     n = 4 * t
     got, _ = _run(box, [n], t=t)
     want = oracle.sweeps27_f64(box, n)
+    assert _same(got, want)
+
+
+@pytest.mark.timeout(600)
+def test_s27_1024cube_bitwise():
+    """The 1024^3 configuration the bench extra times (t=3, 3 rows x 8 waves,
+    sine-mode faces): the whole field after two trips."""
+    print("case s27 1024^3 t=3 x 6", flush=True)
+    box = synth.sine_face_box(1024, 1024, 1024, seed=3)
+    got, info = _run(box, [6], t=3, tile_rows=24, rows_per_wave=3)
+    assert info["tile_rows"] == 24
+    want = oracle.sweeps27_f64(box, 6)
+    del box
     assert _same(got, want)
