@@ -289,7 +289,7 @@ int jacobi_batch_destroy(jacobi_batch_t *h);
  * live in a static device array of the library, JACOBI_NOALLOC_SCRATCH_BYTES
  * per GPU, held until the process ends; the field may need up to
  * JACOBI_NOALLOC_SCRATCH_BYTES / 16 reduction blocks, i.e.
- * ceil(nx/64) * ceil(ny/4) <= 65536 (larger fields: JACOBI_EINVAL).
+ * ceil(nx/62) * ceil(ny/16) <= 65536 (larger fields: JACOBI_EINVAL).
  * Asynchronous on `stream`; the result is bitwise that of jacobi_residual.
  * All calls on one GPU share its array: calls that overlap on one GPU
  * (different streams or threads) race; calls on one stream are ordered.

@@ -100,7 +100,7 @@ struct AuxProblem {
     int64_t px, py;     // pitches of u
     int64_t epx, epy;   // pitches of e / rhs
     int nx, ny, nz;
-    int rtx, rty, rsegs, rseg_len;  // residual tiling (64 x 4 columns x seg)
+    int rtx, rty, rsegs, rseg_len;  // residual tiling (62 x 16 columns x seg)
     int rblocks, rblock_base;       // residual blocks of this problem, prefix
 };
 
@@ -108,7 +108,7 @@ struct AuxProblem {
 int residual_plan(AuxProblem* a);
 
 // Residual r = fold(nbrs) - 6u on the interior of each problem.
-// Pass 1 (k-streaming, one block per 64x4-column tile and k segment) writes
+// Pass 1 (k-streaming, one block per 62x16-column tile and k segment) writes
 // (sum r^2, max|r|) per block into partials[2*b], partials[2*b+1]; pass 2
 // reduces each problem's blocks in fixed order into out[2*q] = ||r||_2,
 // out[2*q+1] = max|r|.  `table` (device) with `count` problems, or `table`

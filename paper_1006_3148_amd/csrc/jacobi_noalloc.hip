@@ -81,7 +81,7 @@ extern "C" int jacobi_residual_noalloc(const double* origin, int64_t px, int64_t
     if (blocks > kMaxBlocks)
         return fail(JACOBI_EINVAL,
                     "residual needs %d reduction blocks; the static scratch holds %lld "
-                    "(ceil(nx/64)*ceil(ny/4) must be <= %lld)",
+                    "(ceil(nx/62)*ceil(ny/16) must be <= %lld)",
                     blocks, (long long)kMaxBlocks, (long long)kMaxBlocks);
     double* partials = nullptr;
     int rc = scratch_ptr(&partials);

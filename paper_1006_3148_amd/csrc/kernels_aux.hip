@@ -9,13 +9,17 @@
 // Compiled with -ffp-contract=off.
 
 #include "internal.h"
+#include "trip_device.h"
 
 namespace jacobi_impl {
 namespace {
 
 constexpr int kRedThreads = 256;
 constexpr int kNoCorrection = -2147483647 - 1;
-constexpr int kRX = 64, kRY = 4;  // residual block: 64 i-lanes x 4 j-rows
+// Residual block: 4 waves of kRR j-rows each; a wave's 64 lanes span 62
+// output i-columns plus one halo column on each side.
+constexpr int kRR = 4;
+constexpr int kRX = 62, kRY = kRR * (kRedThreads / 64);
 
 // Block tree reduction of (sum, max) in a fixed order.
 __device__ __forceinline__ void block_reduce(double& sum, double& mx,
@@ -51,12 +55,14 @@ __device__ __forceinline__ const AuxProblem* find_rblock(const AuxProblem* tab,
     return tab + lo;
 }
 
-// Pass 1: k-streaming residual.  Each thread owns one interior column (i, j)
-// of a 64 x 4 tile and one k segment; the k-1 / k / k+1 values stay in
-// registers, the in-plane neighbours come through L1/L2.  Planes are taken
-// four at a time with every load of the group issued before any use (plane
-// indices clamped to the box, so there is no branch around a load), which
-// keeps four planes of loads in flight per thread.
+// Pass 1: k-streaming residual.  Wave w of a block owns kRR consecutive
+// interior rows j of a 62-column strip and one k segment; lane L holds column
+// i = 62 tx + L (lanes 1..62 are outputs, 0 and 63 their i-halo).  Per plane
+// a wave loads its rows and the row above and below them (kRR + 2 row loads
+// for kRR output rows); i-neighbours come from the adjacent lanes (DPP), j
+// neighbours from the wave's own rows, k-1 / k / k+1 from the rows of three
+// planes.  Planes are loaded four at a time, every load of a group issued
+// before any use, with indices clamped to the box (no branch around a load).
 __global__ __launch_bounds__(kRedThreads) void residual_pass1(
     const AuxProblem* __restrict__ tab, int count, AuxProblem one,
     const int* __restrict__ parity, double* __restrict__ partials)
@@ -69,46 +75,60 @@ __global__ __launch_bounds__(kRedThreads) void residual_pass1(
     const int rest = lb / P->rtx;
     const int ty = rest % P->rty;
     const int sg = rest / P->rty;
-    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
-    const int i = 1 + tx * kRX + lane;
-    const int j = 1 + ty * kRY + row;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = tx * kRX + lane;
+    const int j0 = 1 + ty * kRY + wave * kRR;
     const int k0 = 1 + sg * P->rseg_len;
     const int k1 = min(k0 + P->rseg_len, P->nz + 1);
     const int64_t px = P->px, py = P->py;
+    const int kmax = P->nz + 1;
     const double* __restrict__ u = ((parity && (*parity & 1)) ? P->u[1] : P->u[0]);
+    // Row offsets of rows j0-1 .. j0+kRR (clamped to the box; clamped rows
+    // and columns feed no output).
+    const double* rowp[kRR + 2];
+#pragma unroll
+    for (int r = 0; r < kRR + 2; ++r)
+        rowp[r] = u + (int64_t)min(j0 - 1 + r, P->ny + 1) * px + min(i, P->nx + 1);
+    const bool lane_out = lane >= 1 && lane <= kRX && i <= P->nx;
+    bool out[kRR];
+#pragma unroll
+    for (int r = 0; r < kRR; ++r) out[r] = lane_out && j0 + r <= P->ny;
+
+    // cur: plane k (rows -1..kRR), prev: plane k-1 (output rows)
+    double cur[kRR + 2], prev[kRR];
+#pragma unroll
+    for (int r = 0; r < kRR + 2; ++r) cur[r] = rowp[r][(int64_t)k0 * py];
+#pragma unroll
+    for (int r = 0; r < kRR; ++r) prev[r] = rowp[r + 1][(int64_t)(k0 - 1) * py];
     double sum = 0.0, mx = 0.0;
-    if (i <= P->nx && j <= P->ny) {
-        const double* col = u + (int64_t)j * px + i;
-        const int kmax = P->nz + 1;
-        double um = col[(int64_t)(k0 - 1) * py];
-        double uc = col[(int64_t)k0 * py];
-        for (int k = k0; k < k1; k += 4) {
-            double z[4], w[4], e[4], s_[4], n[4];
+    for (int k = k0; k < k1; k += 4) {
+        double nxt[4][kRR + 2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                z[q] = col[(int64_t)min(k + 1 + q, kmax) * py];
-                const double* c = col + (int64_t)min(k + q, kmax) * py;
-                w[q] = c[-1];
-                e[q] = c[1];
-                s_[q] = c[-px];
-                n[q] = c[px];
-            }
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (k + q < k1) {
-                    double t = w[q];
-                    t = t + e[q];
-                    t = t + s_[q];
-                    t = t + n[q];
-                    t = t + um;
-                    t = t + z[q];
-                    const double r = t - 6.0 * uc;
-                    sum = sum + r * r;
-                    mx = fmax(mx, fabs(r));
+            for (int r = 0; r < kRR + 2; ++r)
+                nxt[q][r] = rowp[r][(int64_t)min(k + 1 + q, kmax) * py];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (k + q < k1) {
+#pragma unroll
+                for (int r = 0; r < kRR; ++r) {
+                    const double c = cur[r + 1];
+                    double t = from_left(c);
+                    t = t + from_right(c);
+                    t = t + cur[r];
+                    t = t + cur[r + 2];
+                    t = t + prev[r];
+                    t = t + nxt[q][r + 1];
+                    const double res = t - 6.0 * c;
+                    sum = out[r] ? sum + res * res : sum;
+                    mx = out[r] ? fmax(mx, fabs(res)) : mx;
                 }
-                um = uc;
-                uc = z[q];
             }
+#pragma unroll
+            for (int r = 0; r < kRR; ++r) prev[r] = cur[r + 1];
+#pragma unroll
+            for (int r = 0; r < kRR + 2; ++r) cur[r] = nxt[q][r];
         }
     }
     block_reduce(sum, mx, sh_sum, sh_max);

@@ -53,7 +53,7 @@ def test_noalloc_residual_matches_handle(first, second):
 
 def test_noalloc_rejects_fields_beyond_the_scratch():
     from paper_1006_3148_amd import lib
-    # ceil(65536/64) * ceil(2048/4) = 524288 blocks > 65536
+    # ceil(65536/62) * ceil(2048/16) = 135424 blocks > 65536
     nx, ny = 65536, 2048
     rc = lib.jacobi_residual_noalloc(256, nx + 2, (nx + 2) * (ny + 2), nx, ny, 4, 256, None)
     assert rc == -1
