@@ -2,7 +2,8 @@
 
     python -m paper_1006_3148_amd.tripbench --n 512 --t 5 --layout ab --sweeps 20
 
-Builds a seeded U[0,1)-boundary box (seed 2, interior 0), creates a handle
+Builds a seeded U[0,1)-boundary box (seed 2, interior 0; n x n x n, or
+n x n x nz with --nz), creates a handle
 with the given configuration, runs one warm-up call and then ``--reps``
 calls of ``--sweeps`` sweeps, and prints one JSON line with the HIP-event
 time per call and the GLUP/s.  ``--t`` may be a comma-separated list: each
@@ -25,6 +26,7 @@ if ROOT not in sys.path:
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--nz", type=int, default=0, help="k extent (0 = n): an n x n x nz box")
     ap.add_argument("--t", default="5")
     ap.add_argument("--layout", default="ab")
     ap.add_argument("--dtype", default="f64")
@@ -41,7 +43,8 @@ def main(argv=None):
     import synth
     from paper_1006_3148_amd import Jacobi
     torch.cuda.set_device(0)
-    box = torch.from_numpy(synth.uniform_box(a.n, a.n, a.n, seed=2)).cuda()
+    nz = a.nz if a.nz > 0 else a.n
+    box = torch.from_numpy(synth.uniform_box(a.n, a.n, nz, seed=2)).cuda()
     for t in [int(v) for v in a.t.split(",")]:
         sweeps = a.sweeps if a.sweeps > 0 else 4 * t
         j = Jacobi(box, t=t, layout=a.layout, dtype=a.dtype, tile_rows=a.tile_rows,
@@ -58,11 +61,11 @@ def main(argv=None):
         ms = ev[0].elapsed_time(ev[1]) / a.reps
         info = j.info()
         j.close()
-        print(json.dumps({"n": a.n, "t": t, "layout": a.layout, "dtype": a.dtype,
+        print(json.dumps({"n": a.n, "nz": nz, "t": t, "layout": a.layout, "dtype": a.dtype,
                           "stencil": a.stencil, "rows_per_wave": a.rows_per_wave,
                           "sweeps_per_call": sweeps, "tile_rows": info["tile_rows"],
                           "seg_len": info["seg_len"], "ms_per_call": round(ms, 4),
-                          "glups": round(a.n ** 3 * sweeps / (ms * 1e-3) / 1e9, 1)}),
+                          "glups": round(a.n * a.n * nz * sweeps / (ms * 1e-3) / 1e9, 1)}),
               flush=True)
 
 
