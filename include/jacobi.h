@@ -129,7 +129,12 @@ typedef struct {
                             t in 1..4; t = 0 autotunes as above among the
                             27-point candidates (t = 2 until then);
                             jacobi_residual and jacobi_solve return
-                            JACOBI_EUNSUPPORTED */
+                            JACOBI_EUNSUPPORTED.  Its compiled tile shapes
+                            (t, tile_rows, rows_per_wave): (1,32,4),
+                            (2,32,4), (2,36,3), (2,32,2), (3,24,3),
+                            (3,32,4), (4,24,3); the defaults for t = 1..4
+                            are (1,32,4), (2,36,3), (3,24,3), (4,24,3)
+                            (jacobi_tile_supported answers for Eq. (1)) */
 } jacobi_desc;
 
 typedef struct jacobi_s jacobi_t;
