@@ -132,6 +132,13 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     constexpr int OX = 64 - 2 * T;
     constexpr int OY = H - 2 * T;
     constexpr int NB = Xch<Real, T, W>::nbuf;
+    // Issuing all of a step's edge-row reads right after the barrier (so
+    // that their latency is paid once per step, not once per stage) holds 2T
+    // more values; shapes whose stage state already fills the register
+    // budget of their occupancy (256, 168, 128 VGPRs for 8, 12, 16 waves)
+    // read per stage instead.
+    constexpr bool HOIST =
+        !KREV && (S27 ? T * R <= 9 : T * R <= (W <= 8 ? 24 : W <= 12 ? 12 : 10));
     constexpr int NR = RHS ? 2 * T - 1 : 1;  // rhs planes held per row
     // Steps per unrolled chunk: PF, so that the prefetch slot of every step
     // is a compile-time constant (no register copies of loads in flight).
@@ -408,10 +415,20 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
                 __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
+            Real upv[HOIST ? T : 1], dnv[HOIST ? T : 1];
+            if constexpr (HOIST) {
+#pragma unroll
+                for (int s = T - 1; s >= 0; --s) {
+                    upv[s] = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+                    dnv[s] = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+                }
+            }
 #pragma unroll
             for (int s = T - 1; s >= 0; --s) {
-                const Real up = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
-                const Real dn = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+                const Real up =
+                    HOIST ? upv[HOIST ? s : 0] : buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+                const Real dn =
+                    HOIST ? dnv[HOIST ? s : 0] : buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
                 const Real hup = from_left(up) + from_right(up);
                 const Real e0 = update27(s, 0, up, hup, X[s][1], LX[s][1], RX[s][1], HX[s][0]);
                 const Real e1 = update27(s, R - 1, X[s][R - 2], HX[s][R - 2], dn,
@@ -439,11 +456,20 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
         }
         __syncthreads();
         // Rows 0 and R-1 take their outer neighbours from the waves above
-        // and below.
+        // and below (read all at once when HOIST).
+        Real upv[HOIST ? T : 1], dnv[HOIST ? T : 1];
+        if constexpr (HOIST) {
+#pragma unroll
+            for (int s = T - 1; s >= 0; --s) {
+                upv[s] = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+                dnv[s] = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+            }
+        }
 #pragma unroll
         for (int s = T - 1; s >= 0; --s) {
-            const Real up = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
-            const Real dn = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+            const Real up = HOIST ? upv[HOIST ? s : 0] : buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+            const Real dn =
+                HOIST ? dnv[HOIST ? s : 0] : buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
             const Real e0 = update(s, 0, up, R > 1 ? X[s][R > 1 ? 1 : 0] : dn);
             const Real e1 = R > 1 ? update(s, R - 1, X[s][R > 1 ? R - 2 : 0], dn) : e0;
             X[s + 1][0] = e0;
