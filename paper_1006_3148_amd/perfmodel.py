@@ -15,14 +15,19 @@ two sides are:
   step.  Ghost zones make the computed cells exceed the owned ones by
   64*H / ((64-2T)(H-2T)), and that is the GPU's price for keeping every
   stage on one CU.  LDS carries 3T instructions (4T x 512 bytes) per wave
-  per step, well below its bandwidth.
+  per step, well below its bandwidth; in the shapes that issue a step's
+  edge-row reads together right after the barrier (the kernel's register
+  rule: T*R <= 24, 12, 10 for 8, 12, 16 waves) the compiler pairs some of the
+  2T reads into one instruction, so T to 2T reads remain.
 
 Prediction for a trip: t_valu = (VALU wave-instructions x 4 cycles) /
 (1024 SIMDs x f x e) and t_hbm = bytes / BW, combined as
 (t_valu^p + t_hbm^p)^(1/p).  The two throughputs overlap imperfectly, so
 the combination is smooth rather than a plain max.  a, b, c come from
-SQ_INSTS_VALU.  phi (the fraction of halo reads that miss L2), e and p are
-fitted once to the measured t = 1..8 sweep at 512^3
+SQ_INSTS_VALU.  phi (the fraction of halo reads that miss L2), p and the
+VALU efficiency e (one value for the shapes with batched edge-row reads, one
+for the others, since the batching removes per-stage LDS stalls) are fitted
+once to the measured t = 1..8 sweep at 512^3
 (profiles/trip_sweep_512.json), with BW the bandwidth the stencil streams at
 (fitted between 70 % and 100 % of the copy probe's 5.52 TB/s).
 
@@ -47,6 +52,8 @@ SIMDS = 4 * CUS
 CLOCK_HZ = 2.4e9
 LDS_BYTES_PER_CLK = 128
 PF = 2  # steps per unrolled chunk of the trip kernel
+E_MAX = 0.75  # highest measured VALU issue share of a SIMD (SQ counters, 512^3: 0.73 for
+#                the 7-point t=5 kernel, 0.75 for the 27-point t=3 kernel)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_DATA = os.path.join(os.path.dirname(HERE), "profiles", "trip_sweep_512.json")
@@ -73,6 +80,12 @@ def geometry(n: int, T: int, R: int, W: int, seg_len: int) -> dict:
             "wave_steps": tx * ty * steps * W, "planes_loaded": planes,
             "tile_cells": 64 * h, "owned_cells": ox * oy,
             "redundancy": 64.0 * h / (ox * oy)}
+
+
+def batched_reads(T: int, R: int, W: int) -> bool:
+    """True for the shapes whose edge-row LDS reads of a step are issued
+    together (the trip kernel's register rule for the 7-point update)."""
+    return T * R <= (24 if W <= 8 else 12 if W <= 12 else 10)
 
 
 def fit_valu(rows, n):
@@ -102,15 +115,19 @@ def predict(n, T, R, W, seg_len, params):
     a, b, c = params["valu"]
     g = geometry(n, T, R, W, seg_len)
     valu = g["wave_steps"] * (a * T * R + b * T + c)
+    batched = batched_reads(T, R, W)
     lds = g["wave_steps"] * 3 * T
+    lds_min = g["wave_steps"] * (2 * T if batched else 3 * T)
     hb = hbm_bytes(n, T, R, W, seg_len, params["phi"])
-    t_valu = valu * 4 / (SIMDS * CLOCK_HZ * params["e"])
+    e = params["e_batched"] if batched else params["e"]
+    t_valu = valu * 4 / (SIMDS * CLOCK_HZ * e)
     t_lds = g["wave_steps"] * 4 * T * 512 / (CUS * LDS_BYTES_PER_CLK * CLOCK_HZ)
     t_hbm = hb / params["bw"]
     p = params["p"]
     t = (t_valu ** p + t_hbm ** p) ** (1.0 / p)
     t = max(t, t_lds)
-    return {"valu": valu, "lds": lds, "hbm_bytes": hb, "t_valu_us": t_valu * 1e6,
+    return {"valu": valu, "lds": lds, "lds_min": lds_min, "batched": batched,
+            "hbm_bytes": hb, "t_valu_us": t_valu * 1e6,
             "t_hbm_us": t_hbm * 1e6, "t_lds_us": t_lds * 1e6, "time_us": t * 1e6,
             "glups": n ** 3 * T / t / 1e9, "redundancy": g["redundancy"]}
 
@@ -131,17 +148,34 @@ def calibrate(doc, bw=5.52e12):
         if best is None or err < best[0]:
             best = (err, phi)
     params["phi"] = float(best[1])
+    # e, e_batched, p, BW: minimise the worst relative time error over a grid
+    # (vectorised: the VALU and HBM terms of each row at e = BW-scale = 1)
+    base = dict(params, e=1.0, e_batched=1.0, bw=1.0, p=1.0)
+    tv, th, tl, bat, meas = [], [], [], [], []
+    for r in rows:
+        pr = predict(n, r["t"], r["rows_per_wave"], r["waves"], r["seg_len"], base)
+        tv.append(pr["t_valu_us"]); th.append(pr["t_hbm_us"]); tl.append(pr["t_lds_us"])
+        bat.append(pr["batched"]); meas.append(r["mean_us"])
+    tv, th, tl, meas = map(np.array, (tv, th, tl, meas))
+    bat = np.array(bat)
+    # VALU efficiency cannot exceed the share of time a SIMD issues VALU
+    # instructions (E_MAX, measured)
+    E = np.linspace(0.5, E_MAX, 24)
     best = None
     for bw_fit in np.linspace(0.70 * bw, bw, 16):
+        thb = th / bw_fit
         for p in np.linspace(1.0, 6.0, 26):
-            for e in np.linspace(0.5, 1.0, 26):
-                params.update(p=float(p), e=float(e), bw=float(bw_fit))
-                err = max(abs(predict(n, r["t"], r["rows_per_wave"], r["waves"], r["seg_len"],
-                                      params)["time_us"] - r["mean_us"]) / r["mean_us"]
-                          for r in rows)
-                if best is None or err < best[0]:
-                    best = (err, float(p), float(e), float(bw_fit))
-    params.update(p=best[1], e=best[2], bw=best[3], max_time_err=best[0])
+            for e in E:
+                # rows without batched reads depend on e only
+                t_o = np.maximum((((tv / e) ** p + thb ** p) ** (1.0 / p)), tl)
+                err_o = np.max(np.abs(t_o[~bat] - meas[~bat]) / meas[~bat], initial=0.0)
+                for eb in E:
+                    t_b = np.maximum((((tv / eb) ** p + thb ** p) ** (1.0 / p)), tl)
+                    err = max(err_o, np.max(np.abs(t_b[bat] - meas[bat]) / meas[bat],
+                                            initial=0.0))
+                    if best is None or err < best[0]:
+                        best = (float(err), float(p), float(e), float(eb), float(bw_fit))
+    params.update(p=best[1], e=best[2], e_batched=best[3], bw=best[4], max_time_err=best[0])
     return params
 
 
@@ -158,7 +192,8 @@ def report(path=DEFAULT_DATA):
         out.append({"t": r["t"], "tile": "%dx%d" % (r["rows_per_wave"], r["waves"]),
                     "redundancy": round(pr["redundancy"], 3),
                     "valu_pred": pr["valu"], "valu_meas": r["SQ_INSTS_VALU"],
-                    "lds_pred": pr["lds"], "lds_meas": r["SQ_INSTS_LDS"],
+                    "lds_pred": pr["lds"], "lds_pred_min": pr["lds_min"],
+                    "lds_meas": r["SQ_INSTS_LDS"], "batched": pr["batched"],
                     "hbm_pred": pr["hbm_bytes"], "hbm_meas": meas_bytes,
                     "t_valu_us": round(pr["t_valu_us"], 1), "t_hbm_us": round(pr["t_hbm_us"], 1),
                     "t_lds_us": round(pr["t_lds_us"], 1),
@@ -172,10 +207,10 @@ def main(argv=None):
     argv = sys.argv[1:] if argv is None else argv
     params, rows = report(argv[0] if argv else DEFAULT_DATA)
     a, b, c = params["valu"]
-    print("VALU per wave per step = %.2f T R %+.2f T %+.2f;  phi = %.2f, e = %.2f, p = %.2f, "
-          "BW = %.2f TB/s; worst time error %.1f %%" % (
-              a, b, c, params["phi"], params["e"], params["p"], params["bw"] / 1e12,
-              100 * params["max_time_err"]))
+    print("VALU per wave per step = %.2f T R %+.2f T %+.2f;  phi = %.2f, e = %.2f "
+          "(batched edge-row reads: %.2f), p = %.2f, BW = %.2f TB/s; worst time error %.1f %%" % (
+              a, b, c, params["phi"], params["e"], params["e_batched"], params["p"],
+              params["bw"] / 1e12, 100 * params["max_time_err"]))
     print("| t | tile | redundancy | VALU pred/meas | LDS pred/meas | HBM GB pred/meas | "
           "t_valu us | t_hbm us | t_lds us | time pred/meas us | GLUP/s pred/meas |")
     print("|---|---|---|---|---|---|---|---|---|---|---|")

@@ -16,7 +16,12 @@ def test_model_reproduces_counters_and_times():
         g = pm.geometry(512, m["t"], m["rows_per_wave"], m["waves"], m["seg_len"])
         assert g["waves"] == m["SQ_WAVES"]
         assert abs(r["valu_pred"] / r["valu_meas"] - 1) < 0.015, r
-        assert abs(r["lds_pred"] / r["lds_meas"] - 1) < 0.005, r
+        if r["batched"]:
+            # T writes and between T and 2T reads per wave and step (the
+            # compiler pairs some of the batched reads)
+            assert r["lds_pred_min"] * 0.995 <= r["lds_meas"] <= r["lds_pred"] * 1.005, r
+        else:
+            assert abs(r["lds_pred"] / r["lds_meas"] - 1) < 0.005, r
         assert abs(r["hbm_pred"] / r["hbm_meas"] - 1) < 0.06, r
         assert abs(r["time_pred_us"] / r["time_meas_us"] - 1) < 0.10, r
     # about 11 VALU instructions per cell-stage: 5 adds, 1 multiply, 4 DPP
