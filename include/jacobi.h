@@ -97,8 +97,10 @@ typedef struct {
                             jacobi_sweep of >= 96 sweeps times the candidate
                             (t, tile) configurations on real sweeps, keeps the
                             fastest; t = 5 until then), else 4 */
-    int32_t tile_rows;   /* j-rows per tile: 0 = default for t, else one of
-                            the compiled shapes (jacobi_tile_supported) */
+    int32_t tile_rows;   /* j-rows per tile: 0 = default for t (for A/B FP64
+                            trips of t = 5 the planner picks the 4x8 or the
+                            3x12 shape by box size), else one of the
+                            compiled shapes (jacobi_tile_supported) */
     int32_t rows_per_wave; /* 0 = default; with tile_rows selects the shape */
     int32_t seg_len;     /* k planes per tile segment, 0 = automatic;
                             COMPRESSED needs >= 2t, and caps E (below) at

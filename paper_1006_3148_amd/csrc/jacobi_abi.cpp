@@ -272,6 +272,17 @@ int compressed_zextra(const jacobi_desc* d, int t)
     return E;
 }
 
+// Alternative A/B FP64 tile shape for T = 5, and the planning cost of a trip:
+// rounds of concurrent tiles (one workgroup per CU) x steps of one tile x
+// tile rows.
+constexpr TripConfig kAltCfg5{5, 3, 12};
+double plan_cost(const Plan& p)
+{
+    const int T = p.cfg.T;
+    const int64_t rounds = (p.ntiles + kCUs - 1) / kCUs;
+    return (double)rounds * (p.seg_len + 3 * T) * (p.cfg.R * p.cfg.W);
+}
+
 int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                       Layout* lay)
 {
@@ -325,7 +336,8 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
     int64_t max_tiles = 0;
     for (int T = 1; T <= t; ++T) {
         TripConfig cfg = default_cfg(T, comp, s27);
-        if (T == t && !mg && (d->tile_rows > 0 || d->rows_per_wave > 0)) {
+        const bool shape_given = T == t && !mg && (d->tile_rows > 0 || d->rows_per_wave > 0);
+        if (shape_given) {
             const int R = d->rows_per_wave > 0 ? d->rows_per_wave : 4;
             const int rows = d->tile_rows > 0 ? d->tile_rows : cfg.R * cfg.W;
             if (rows % R != 0)
@@ -343,6 +355,18 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                         "tile shape t=%d rows=%d cannot cover this box%s", T,
                         cfg.R * cfg.W,
                         comp ? " (compressed needs tiles and segments >= 2t)" : "");
+        // A/B FP64 trips of T = 5: the 3x12 tile (three waves per SIMD) costs
+        // per row and step what the 4x8 tile (two waves) does, so the shape
+        // with fewer rounds x steps x rows wins (4x8 at 512^3: one generation
+        // of 240 tiles; 3x12 at 1024^3: 3 rounds of one 1026-plane segment
+        // against 7 of two).
+        if (T == 5 && !shape_given && !comp && !s27 && !mg && d->dtype == JACOBI_F64) {
+            Plan alt;
+            if (make_plan(d->nx, d->ny, d->nz, kAltCfg5, T == t ? d->seg_len : 0, false, kCUs,
+                          &alt) &&
+                plan_cost(alt) < plan_cost(plans[T]))
+                plans[T] = alt;
+        }
         max_tiles = std::max<int64_t>(max_tiles, plans[T].ntiles);
     }
     if (tune) {

@@ -136,9 +136,11 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
     // that their latency is paid once per step, not once per stage) holds 2T
     // more values; shapes whose stage state already fills the register
     // budget of their occupancy (256, 168, 128 VGPRs for 8, 12, 16 waves)
-    // read per stage instead.
+    // read per stage instead.  Compressed trips carry more state (progress
+    // words; the mirrored view's extra plane).
     constexpr bool HOIST =
-        !KREV && (S27 ? T * R <= 9 : T * R <= (W <= 8 ? 24 : W <= 12 ? 12 : 10));
+        !KREV && (S27 ? T * R <= 9
+                      : T * R <= (W <= 8 ? 24 : W <= 12 ? (FLAGS ? 12 : 15) : 10));
     constexpr int NR = RHS ? 2 * T - 1 : 1;  // rhs planes held per row
     // Steps per unrolled chunk: PF, so that the prefetch slot of every step
     // is a compile-time constant (no register copies of loads in flight).

@@ -17,7 +17,7 @@ two sides are:
   stage on one CU.  LDS carries 3T instructions (4T x 512 bytes) per wave
   per step, well below its bandwidth; in the shapes that issue a step's
   edge-row reads together right after the barrier (the kernel's register
-  rule: T*R <= 24, 12, 10 for 8, 12, 16 waves) the compiler pairs some of the
+  rule: T*R <= 24, 15, 10 for 8, 12, 16 waves) the compiler pairs some of the
   2T reads into one instruction, so T to 2T reads remain.
 
 Prediction for a trip: t_valu = (VALU wave-instructions x 4 cycles) /
@@ -85,7 +85,7 @@ def geometry(n: int, T: int, R: int, W: int, seg_len: int) -> dict:
 def batched_reads(T: int, R: int, W: int) -> bool:
     """True for the shapes whose edge-row LDS reads of a step are issued
     together (the trip kernel's register rule for the 7-point update)."""
-    return T * R <= (24 if W <= 8 else 12 if W <= 12 else 10)
+    return T * R <= (24 if W <= 8 else 15 if W <= 12 else 10)
 
 
 def fit_valu(rows, n):
