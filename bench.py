@@ -191,7 +191,7 @@ def probe_bw(torch, nbytes=2 << 30, reps=10):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; "
                           "--gpus %d is not supported" % args.gpus}))
         sys.exit(2)
     import numpy as np

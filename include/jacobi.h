@@ -61,7 +61,7 @@ extern "C" {
 typedef enum {
     JACOBI_OK = 0,
     JACOBI_EINVAL = -1,       /* bad argument (null, size, range, alignment) */
-    JACOBI_EUNSUPPORTED = -2, /* valid request this build does not provide */
+    JACOBI_EUNSUPPORTED = -2, /* valid request the library does not support */
     JACOBI_EWORKSPACE = -3,   /* workspace missing or too small */
     JACOBI_EHIP = -4,         /* HIP runtime error (launch or kernel fault) */
     JACOBI_ETIMEOUT = -5,     /* a progress-flag wait exceeded its spin bound */

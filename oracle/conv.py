@@ -1,7 +1,7 @@
 """FP64 reference of the learned-initial-guess network -- TEST ORACLE.
 
 The learned initial guess is not in the paper: it supplies a starting field for
-the Jacobi method of Sect. 1.1.  Architecture (the reading this build takes):
+the Jacobi method of Sect. 1.1.  Architecture (the reading taken here):
 
 * input lift: for interior cell (i,j,k) of an N^3 grid, 16 channels =
   the six face values at its projections onto the boundary faces
