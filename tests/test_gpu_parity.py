@@ -191,6 +191,27 @@ def test_residual_matches_oracle_and_is_deterministic():
     assert m1 == float(np.max(np.abs(oracle.residual_f64(u))))
 
 
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 1), (61, 16, 3), (62, 17, 4),
+                                  (63, 15, 33), (125, 47, 20)])
+def test_residual_block_edges_match_oracle(dims):
+    """The residual's blocks are 62 i-columns (lanes 0 and 63 the halo) by 16
+    j-rows (4 waves of 4) by a k segment: boxes one cell wide, widths around
+    62 and heights around 16 exercise the clamped halo lanes and rows."""
+    from paper_1006_3148_amd import Jacobi
+    box = synth.full_random_box(*dims, seed=600 + sum(dims))
+    print("case residual %s" % (dims,), flush=True)
+    j = Jacobi(box, t=2)
+    r1, m1 = j.residual()
+    j.sweep(3)
+    r2, m2 = j.residual()
+    u = j.box()
+    j.close()
+    for r, m, field in ((r1, m1, box), (r2, m2, u)):
+        ro = oracle.residual_norm(field)
+        assert abs(r - ro) <= 1e-12 * ro, (dims, r, ro)
+        assert m == float(np.max(np.abs(oracle.residual_f64(field)))), dims
+
+
 @pytest.mark.parametrize("layout", ["ab", "compressed"])
 def test_split_of_sweeps_does_not_change_bits(layout):
     from paper_1006_3148_amd import Jacobi
