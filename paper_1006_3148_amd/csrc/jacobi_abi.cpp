@@ -355,15 +355,18 @@ int validate_and_plan(const jacobi_desc* d, Plan* plans, int* t_out,
                         "tile shape t=%d rows=%d cannot cover this box%s", T,
                         cfg.R * cfg.W,
                         comp ? " (compressed needs tiles and segments >= 2t)" : "");
-        // A/B FP64 trips of T = 5: the 3x12 tile (three waves per SIMD) costs
-        // per row and step what the 4x8 tile (two waves) does, so the shape
-        // with fewer rounds x steps x rows wins (4x8 at 512^3: one generation
-        // of 240 tiles; 3x12 at 1024^3: 3 rounds of one 1026-plane segment
-        // against 7 of two).
-        if (T == 5 && !shape_given && !comp && !s27 && !mg && d->dtype == JACOBI_F64) {
+        // Dense trips of T = 5 (A/B FP64, and the FP32 correction trips,
+        // which run on dense grids whatever the FP64 layout): the 3x12 tile
+        // (three waves per SIMD) costs per row and step what the 4x8 tile
+        // (two waves) does, so the shape with fewer rounds x steps x rows
+        // wins (4x8 at 512^3: one generation of 240 tiles; 3x12 at 1024^3:
+        // 3 rounds of one 1026-plane segment against 7 of two).
+        const bool dense_trips = (d->dtype == JACOBI_F64 && !comp) ||
+                                 d->dtype == JACOBI_F32_REFINED;
+        if (T == 5 && !shape_given && !s27 && !mg && dense_trips) {
             Plan alt;
-            if (make_plan(d->nx, d->ny, d->nz, kAltCfg5, T == t ? d->seg_len : 0, false, kCUs,
-                          &alt) &&
+            if (make_plan(d->nx, d->ny, d->nz, kAltCfg5, T == t ? d->seg_len : 0, comp, kCUs,
+                          &alt, comp ? 2 * T + zextra : 0) &&
                 plan_cost(alt) < plan_cost(plans[T]))
                 plans[T] = alt;
         }
