@@ -367,6 +367,30 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
             return e;
         };
 
+        // The outer neighbours of the edge rows: the last row of the wave
+        // above and the first row of the wave below (after the barrier).
+        // With HOIST all of the step's reads are issued at once, in the
+        // order of use, by read_edges; edge_above / edge_below then return
+        // them, else they read LDS per stage.
+        Real upv[HOIST ? T : 1], dnv[HOIST ? T : 1];
+        auto read_edges = [&]() {
+            if constexpr (HOIST) {
+#pragma unroll
+                for (int s = T - 1; s >= 0; --s) {
+                    upv[s] = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+                    dnv[s] = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+                }
+            }
+        };
+        auto edge_above = [&](const int s) -> Real {
+            if constexpr (HOIST) return upv[s];
+            else return buf[s][wave > 0 ? wave - 1 : 0][1][lane];
+        };
+        auto edge_below = [&](const int s) -> Real {
+            if constexpr (HOIST) return dnv[s];
+            else return buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+        };
+
         // 27-point update of row r from the row above (j-1: its value and
         // the sum of its i-neighbours) and the row below (j+1: its i-1 and
         // i+1 neighbours), with hs the sum of row r's own i-neighbours.
@@ -417,20 +441,11 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
                 __builtin_amdgcn_sched_barrier(0);
             }
             __syncthreads();
-            Real upv[HOIST ? T : 1], dnv[HOIST ? T : 1];
-            if constexpr (HOIST) {
-#pragma unroll
-                for (int s = T - 1; s >= 0; --s) {
-                    upv[s] = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
-                    dnv[s] = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
-                }
-            }
+            read_edges();
 #pragma unroll
             for (int s = T - 1; s >= 0; --s) {
-                const Real up =
-                    HOIST ? upv[HOIST ? s : 0] : buf[s][wave > 0 ? wave - 1 : 0][1][lane];
-                const Real dn =
-                    HOIST ? dnv[HOIST ? s : 0] : buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+                const Real up = edge_above(s);
+                const Real dn = edge_below(s);
                 const Real hup = from_left(up) + from_right(up);
                 const Real e0 = update27(s, 0, up, hup, X[s][1], LX[s][1], RX[s][1], HX[s][0]);
                 const Real e1 = update27(s, R - 1, X[s][R - 2], HX[s][R - 2], dn,
@@ -458,20 +473,12 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
         }
         __syncthreads();
         // Rows 0 and R-1 take their outer neighbours from the waves above
-        // and below (read all at once when HOIST).
-        Real upv[HOIST ? T : 1], dnv[HOIST ? T : 1];
-        if constexpr (HOIST) {
-#pragma unroll
-            for (int s = T - 1; s >= 0; --s) {
-                upv[s] = buf[s][wave > 0 ? wave - 1 : 0][1][lane];
-                dnv[s] = buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
-            }
-        }
+        // and below.
+        read_edges();
 #pragma unroll
         for (int s = T - 1; s >= 0; --s) {
-            const Real up = HOIST ? upv[HOIST ? s : 0] : buf[s][wave > 0 ? wave - 1 : 0][1][lane];
-            const Real dn =
-                HOIST ? dnv[HOIST ? s : 0] : buf[s][wave < W - 1 ? wave + 1 : W - 1][0][lane];
+            const Real up = edge_above(s);
+            const Real dn = edge_below(s);
             const Real e0 = update(s, 0, up, R > 1 ? X[s][R > 1 ? 1 : 0] : dn);
             const Real e1 = R > 1 ? update(s, R - 1, X[s][R > 1 ? R - 2 : 0], dn) : e0;
             X[s + 1][0] = e0;
