@@ -35,7 +35,9 @@ struct TripParams {
     int ntiles;
     int mode;          // 0: blockIdx tiles (A/B); 1: tickets + flags
                        // (compressed); 2: batch table, tickets; 3: several
-                       // trips (teams) in one persistent launch (A/B)
+                       // trips (teams) in one persistent launch (A/B);
+                       // 4: segmented tail columns of a split trip (A/B,
+                       // 27-point)
     int dir;           // +1 forward shift (-t), -1 backward shift (+t); mode 1
     int* flags;        // per-tile progress words, stride kFlagStride ints
     int* ticket;       // ticket counter (zeroed before the launch)
@@ -54,9 +56,10 @@ struct TripParams {
                                 // smoother) with weight omega
     float omega;
     int groups;                 // mode 1: per-XCD claim groups (> 1) or one
-                                // ticket counter (1)
+                                // ticket counter (1); mode 4: tail columns
     int chunk;                  // mode 1 groups: tiles per chunk (set at
-                                // launch); mode 0: > 0 selects band order
+                                // launch); mode 0: > 0 selects band order;
+                                // mode 4: first tail column
     int* gcnt;                  // mode 1 groups: kClaimGroups counters, stride
                                 // kFlagStride ints (zeroed)
     int zshift;                 // mode 1: k shift of dst against src

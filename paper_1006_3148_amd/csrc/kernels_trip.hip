@@ -41,7 +41,8 @@ bool trip_config_supported_s27(const TripConfig& c)
 hipError_t launch_trip_f64(const TripConfig& c, const TripParams& p,
                            hipStream_t s)
 {
-    if (p.s27) return p.mode == 0 ? trip_dispatch_f64_s27(c, p, s) : hipErrorInvalidValue;
+    if (p.s27)
+        return p.mode == 0 || p.mode == 4 ? trip_dispatch_f64_s27(c, p, s) : hipErrorInvalidValue;
     switch (p.mode) {
     case 0: return trip_dispatch_f64_m0(c, p, s);
     case 1: return p.krev ? trip_dispatch_f64_m1r(c, p, s) : trip_dispatch_f64_m1(c, p, s);

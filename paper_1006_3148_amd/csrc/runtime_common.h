@@ -20,6 +20,10 @@ constexpr int kCUs = 256;  // MI355X compute units
 struct Plan {
     TripConfig cfg{1, 4, 16};
     int tiles_x = 0, tiles_y = 0, segs = 0, seg_len = 0, ntiles = 0;
+    // Split trip (A/B, 27-point): the first ntiles columns run whole (one
+    // segment), then tail_cols columns from column ntiles on run in a second
+    // launch, in segments of tail_len planes (tail_tiles tiles).
+    int tail_cols = 0, tail_len = 0, tail_tiles = 0;
 };
 
 // Default tile shape for T sweeps per trip (register state fits without

@@ -121,10 +121,11 @@ struct Xch {
 //     + 1/128 (C(q-2) + C(q)).
 // The window moves along k like the 7-point one: a stage keeps, per cell,
 // the folds started by planes q-1 and q-2 and the three sums of plane q-1.
+// KR: the tile's column over planes [kb, ke) instead of its segment.
 template <typename Real, int T, int R, int W, int PF, bool RHS, bool FLAGS, bool EDGE,
-          bool WT = false, bool KREV = false, bool S27 = false>
+          bool WT = false, bool KREV = false, bool S27 = false, bool KR = false>
 __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int tile,
-                                         Real (*xch)[T][W][2][64])
+                                         Real (*xch)[T][W][2][64], int kb = 0, int ke = 0)
 {
     static_assert(!S27 || (!RHS && !FLAGS && !WT && !KREV && R >= 2),
                   "the 27-point update is built for plain A/B sweeps with R >= 2");
@@ -158,8 +159,8 @@ __device__ __forceinline__ void run_tile(const TripParams& p, const Geo& g, int 
 
     const int i = tx * OX - T + lane;
     const int j0 = ty * OY - T + wave * R;
-    const int k0 = seg * g.seg_len;
-    const int k1 = min(k0 + g.seg_len, g.nz + 2);
+    const int k0 = KR ? kb : seg * g.seg_len;
+    const int k1 = KR ? ke : min(k0 + g.seg_len, g.nz + 2);
     const int a = max(k0 - T, 0);
     const int b = min(k1 - 1 + T, g.nz + 1);
     // Stage s (1-based) completes plane a+n-2s+1 in step n; the last output
@@ -632,6 +633,9 @@ __device__ __forceinline__ void finish_team(const TripParams& p, int tile, int t
 //         items (team, tile) from one ticket counter in team-major order,
 //         so every item an item waits for has a smaller ticket (no
 //         deadlock, whatever number of workgroups is resident).
+// MODE 4: one problem (A/B), the tail of a trip whose first columns ran
+//         whole in a MODE 0 launch: p.groups columns from column p.chunk on,
+//         in segments of p.seg_len planes, one tile per workgroup.
 template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool WT = false,
           bool KREV = false, bool S27 = false>
 __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
@@ -646,9 +650,17 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
     for (int iter = 0;; ++iter) {
         int tile;
         int team = 0;
+        int kb = 0, ke = 0;  // MODE 4: the tile's planes
         if (MODE == 0) {
             if (iter > 0) return;
             tile = p.chunk > 0 ? band_tile(blockIdx.x, p.ntiles) : xcd_tile(blockIdx.x, p.ntiles);
+        } else if (MODE == 4) {
+            if (iter > 0) return;
+            const int local = xcd_tile(blockIdx.x, p.ntiles);
+            const int sg = local / p.groups;
+            tile = p.chunk + (local - sg * p.groups);
+            kb = sg * p.seg_len;
+            ke = min(kb + p.seg_len, p.nz + 2);
         } else {
             __syncthreads();  // previous tile finished with tile_sh and xch
             if (threadIdx.x == 0)
@@ -727,10 +739,18 @@ __global__ __launch_bounds__(64 * W) void trip_kernel(TripParams p)
         if (MODE == 3 && team > 0)
             wait_team(p.flags, p.done, p.err, p.tiles_x, p.tiles_y, p.segs, p.ntiles,
                       p.looseness, p.spin_limit, tile, team);
-        if (interior_tile)
+        if constexpr (MODE == 4) {
+            if (interior_tile)
+                run_tile<Real, T, R, W, PF, RHS, FLAGS, false, WT, KREV, S27, true>(p, g, tile,
+                                                                                     xch, kb, ke);
+            else
+                run_tile<Real, T, R, W, PF, RHS, FLAGS, true, WT, KREV, S27, true>(p, g, tile,
+                                                                                    xch, kb, ke);
+        } else if (interior_tile) {
             run_tile<Real, T, R, W, PF, RHS, FLAGS, false, WT, KREV, S27>(p, g, tile, xch);
-        else
+        } else {
             run_tile<Real, T, R, W, PF, RHS, FLAGS, true, WT, KREV, S27>(p, g, tile, xch);
+        }
         if (MODE == 3) finish_team(p, tile, team);
     }
 }
@@ -741,8 +761,8 @@ template <typename Real, int T, int R, int W, int PF, bool RHS, int MODE, bool W
 hipError_t launch_mode(const TripParams& p, hipStream_t s)
 {
     const dim3 block(64 * W);
-    if constexpr (MODE == 0) {
-        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, 0, WT, false, S27>),
+    if constexpr (MODE == 0 || MODE == 4) {
+        hipLaunchKernelGGL((trip_kernel<Real, T, R, W, PF, RHS, MODE, WT, false, S27>),
                            dim3(p.ntiles), block, 0, s, p);
         return hipGetLastError();
     }

@@ -153,3 +153,41 @@ def test_s27_1024cube_bitwise():
     want = oracle.sweeps27_f64(box, 6)
     del box
     assert _same(got, want)
+
+
+@pytest.mark.parametrize("t,dims,split", [
+    (3, (70, 45, 37), "4"), (4, (70, 45, 37), "4"), (2, (130, 67, 21), "4"),
+    (2, (200, 150, 90), "8"), (3, (150, 40, 300), "4"), (4, (64, 64, 64), "4"),
+    (3, (120, 90, 50), "4"), (3, (70, 45, 37), "0"), (3, (1, 1, 1), "4")])
+def test_s27_split_trips_bitwise(t, dims, split, monkeypatch):
+    """Split trips: the first multiple-of-n tile columns run whole in one
+    launch, the columns left in a second launch, cut into segments of at
+    least 2t planes (JACOBI_KSPLIT=n forces it with rounds of n columns; 0
+    turns it off); remainder trips and uneven calls included."""
+    monkeypatch.setenv("JACOBI_KSPLIT", split)
+    box = synth.full_random_box(*dims, seed=360 + t)
+    calls = [2 * t + 1, 3]
+    print("case s27 split=%s t=%d dims=%s calls=%s" % (split, t, dims, calls), flush=True)
+    got, _ = _run(box, calls, t=t)
+    _assert_same(got, oracle.sweeps27_f64(box, sum(calls)),
+                 "s27 split=%s t=%d %s" % (split, t, dims))
+
+
+def test_s27_split_graph_and_autotune_bitwise(monkeypatch):
+    monkeypatch.setenv("JACOBI_KSPLIT", "4")
+    from paper_1006_3148_amd import Jacobi
+    box = synth.uniform_box(120, 90, 50, seed=362)
+    print("case s27 split graph replay + autotune", flush=True)
+    j = Jacobi(box, t=3, layout="ab", stencil=27, use_graph=True)
+    want = box
+    for q in range(3):
+        j.sweep(7)
+        want = oracle.sweeps27_f64(want, 7)
+        _assert_same(j.box(), want, "s27 split replay %d" % q)
+    j.close()
+    j = Jacobi(box, t=0, layout="ab", stencil=27)
+    j.sweep(100)
+    j.sweep(7)
+    got = j.box()
+    j.close()
+    _assert_same(got, oracle.sweeps27_f64(box, 107), "s27 split autotune")
