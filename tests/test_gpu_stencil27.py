@@ -137,7 +137,10 @@ def test_s27_512cube_bitwise(t):
     print("case s27 512^3 t=%d" % t, flush=True)
     box = synth.uniform_box(512, 512, 512, seed=2)
     n = 4 * t
-    got, _ = _run(box, [n], t=t)
+    got, info = _run(box, [n], t=t)
+    # t=3: 261 tile columns, planned as a split trip (256 whole columns of
+    # 514 planes, then the 5 left); t=2: equal segments
+    assert (info["seg_len"] == 514) == (t == 3), info
     want = oracle.sweeps27_f64(box, n)
     assert _same(got, want)
 
